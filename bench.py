@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the FCN z-step on one MI355X, in grid-point z-steps per second.
+
+Workload: the full-model pulse (Nr=512 over [0, 8 mm], Nt=2048 over [-400, 400) fs,
+w0 = 2 mm, tau = 100 fs, P = 5 Pcr, Kerr n2 + n4, 8-photon ionisation with plasma
+defocusing, multiphoton and collisional absorption, dz = 5 mm), in the FP32 field
+precision with FP64 density scan and diagnostics.  One step is one whole Strang z-step
+(column CN solve + fused iFFT / two nonlinear half steps / FFT row pass, diagnostics
+partials included) on the resident field.  The line also carries the FP64 plain method
+on the same workload, the FP32 error against it after the workload's 2000 steps, the
+roofline of the dominant kernel and the CPU oracle's rate on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "grid-pt z-steps/s, FP32/parareal vs FP64 plain at 1e-5 rel err; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def weighted_rel_err(a, ref):
+    nr = ref.shape[0]
+    w = np.arange(nr, dtype=np.float64)
+    w[0] = 0.125
+    w[-1] = 0.0
+    return math.sqrt(np.sum(w[:, None] * np.abs(a - ref) ** 2) / np.sum(w[:, None] * np.abs(ref) ** 2))
+
+
+def timed_steps(plan, field, steps, torch):
+    """K steps bracketed by device synchronisation; returns seconds."""
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    plan.step(field, steps)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return max(wall, start.elapsed_time(end) * 1e-3)
+
+
+def cpu_baseline(inst, a0, seconds: float):
+    """The FP64 oracle on the host cores over a bounded sample of the same workload."""
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    pts = int(inst["nr"]) * int(inst["nt"])
+    t0 = time.perf_counter()
+    a = oracle.propagate(inst, a0, 1, threads=threads)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(2000, int(seconds / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.propagate(inst, a, n, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": pts * n / dt, "unit": "grid-pt z-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} FP64 oracle steps of the {inst['nr']}x{inst['nt']} full-model pulse "
+                      f"(after 1 warm step), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: this build runs the "
+              "z-step on a single MI355X (multi-GPU sharding is a design note, not implemented).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 2:
+        print("--steps must be >= 2", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1507_05988_amd import fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    inst = wl.config_full()
+    pts = int(inst["nr"]) * int(inst["nt"])
+    a0 = wl.gaussian_field(inst)
+
+    # ---- FP32 timed region
+    p32 = fcn.Plan(inst, precision="fp32")
+    f32 = p32.pack(a0.astype(np.complex64))
+    if args.warmup > 0:
+        p32.step(f32, args.warmup)
+    sec = timed_steps(p32, f32, args.steps, torch)
+    p32.sync()
+    value = pts * args.steps / sec
+    ms_per_step = sec * 1e3 / args.steps
+    print(f"[bench] fp32 {args.steps} steps in {sec:.4f} s ({ms_per_step * 1e3:.2f} us/step)", file=sys.stderr,
+          flush=True)
+
+    # ---- per-kernel durations with HIP events on the plan's stream
+    krow, kcol, _ = p32.step_timed(f32, min(args.steps, 2000))
+    p32.sync()
+    bytes_per_launch = pts * 2 * 8  # each pass reads and writes every FP32 complex value once
+    dom_name, dom_ms = ("row_kernel (iFFT + 2 NL half steps + FFT)", krow) if krow >= kcol else \
+        ("col_kernel (CN solve)", kcol)
+    achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "kernel_ms": round(dom_ms, 6), "row_ms": round(krow, 6), "col_ms": round(kcol, 6),
+                "bytes_per_launch": bytes_per_launch}
+    print(f"[bench] kernel means: row {krow * 1e3:.2f} us, col {kcol * 1e3:.2f} us", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "grid-pt z-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "full-model pulse, FP32 field / FP64 density, Nr=512, Nt=2048, dz=5 mm",
+                   "nr": int(inst["nr"]), "nt": int(inst["nt"]), "dz": inst["dz"], "P_over_Pcr": 5.0,
+                   "terms": "diffraction+GVD+Kerr(n2,n4)+plasma+MPA(K=8)+collisions"},
+        "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1),
+        "roofline": roofline,
+    }
+
+    # ---- FP64 plain method on the same workload
+    if not args.no_fp64:
+        p64 = fcn.Plan(inst, precision="fp64")
+        f64 = p64.pack(a0)
+        p64.step(f64, min(args.warmup, 50) or 1)
+        n64 = min(args.steps, 1000)
+        s64 = timed_steps(p64, f64, n64, torch)
+        p64.sync()
+        r64, c64, _ = p64.step_timed(f64, min(n64, 1000))
+        out["fp64_plain"] = {"value": round(pts * n64 / s64, 1), "ms_per_step": round(s64 * 1e3 / n64, 6),
+                             "steps": n64, "row_ms": round(r64, 6), "col_ms": round(c64, 6),
+                             "hbm_gbs_algorithmic": round(pts * n64 / s64 * 64 / 1e9, 1)}
+        del p64, f64
+
+    # ---- FP32 error against the FP64 GPU method over the workload's 2000 steps
+    if not args.no_accuracy:
+        nacc = wl.FULL_STEPS
+        q32 = fcn.Plan(inst, precision="fp32")
+        q64 = fcn.Plan(inst, precision="fp64")
+        g32 = q32.pack(a0.astype(np.complex64))
+        g64 = q64.pack(a0)
+        d32 = q32.propagate(g32, nacc, diag_every=nacc)
+        d64 = q64.propagate(g64, nacc, diag_every=nacc)
+        q32.sync()
+        q64.sync()
+        x32 = q32.unpack(g32)[0].astype(np.complex128)
+        x64 = q64.unpack(g64)[0]
+        r32 = q32.split_diag(d32[-1])[0]
+        r64 = q64.split_diag(d64[-1])[0]
+        out["accuracy_fp32_vs_fp64"] = {
+            "steps": nacc, "z_m": r64["z"],
+            "field": weighted_rel_err(x32, x64),
+            "fluence": float(np.max(np.abs(r32["fluence"] - r64["fluence"])) / np.max(r64["fluence"])),
+            "rho_max": abs(r32["rho_max"] - r64["rho_max"]) / max(r64["rho_max"], 1e-300),
+            "energy": abs(r32["energy"] / r64["energy"] - 1),
+            "rho_max_fp64": r64["rho_max"], "i_max_fp64": r64["i_max"],
+        }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, a0, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * fcn.h -- C ABI of the MI355X (gfx950) implementation of the 2D+1 split-step Fourier /
+ * Crank-Nicholson (FCN) z-step of Ma & Lin, "Parallel simulation for the ultra-short laser
+ * pulses' propagation in air" (arXiv:1507.05988).
+ *
+ * The paper's serial method (Sec. 3, closing summary) is: input the pulse, the equation
+ * coefficients, the r and t ranges and the grid steps; precompute the tridiagonal matrices
+ * M_abc^p, M_def^p for every frequency; then loop over z.  Here that maps to
+ * fcn_plan_create (input + precompute what does not depend on the field), fcn_step (the
+ * z loop) and fcn_propagate (the z loop with diagnostics and adaptive step lengths).
+ *
+ * Conventions shared by every entry point
+ *  - Units are SI.  Plain pointers and sizes only; no C++ or torch types cross this ABI.
+ *  - Field layout: one flat buffer of complex values, interleaved (re, im), for all
+ *    instances of a plan; instance i starts at the element offset fcn_field_offset(i) and
+ *    is a row-major [nr][nt] matrix with t contiguous: element (m, p) is A(r_m, t_p) with
+ *    r_m = m r_max/(nr-1) and t_p = t_min + p (t_max - t_min)/nt (Sec. 3, the grid
+ *    A_{m,p}).  Precision FCN_FP64 uses double2 elements, FCN_FP32 float2 elements.
+ *    Between calls the field is in the time domain at an integer z-step.
+ *  - Ownership: the caller allocates and frees every device buffer (field, workspace,
+ *    diagnostics, dz log) and owns the HIP stream.  After fcn_plan_bind the library never
+ *    allocates device memory.  Plans own only host memory and are freed by
+ *    fcn_plan_destroy.
+ *  - Asynchrony: compute entry points enqueue work on the bound stream and return at once.
+ *    Argument errors are reported synchronously by the return code; numerical failure
+ *    (a non-finite intensity seen on the device) is reported by fcn_sync.
+ *  - A plan is not thread-safe.  fcn_last_error(plan) gives a text for the last failure.
+ */
+#ifndef FCN_H
+#define FCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcn_plan_s *fcn_plan_t;
+
+typedef enum {
+    FCN_OK = 0,
+    FCN_E_ARG = 1,         /* invalid argument or parameter value */
+    FCN_E_SIZE = 2,        /* workspace too small, or a size outside the supported range */
+    FCN_E_HIP = 3,         /* a HIP runtime call failed */
+    FCN_E_NONFINITE = 4,   /* the device saw a non-finite intensity */
+    FCN_E_STATE = 5,       /* call order violated (e.g. step before bind) */
+    FCN_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} fcn_status;
+
+/* Term switches of the operators (Eqs. linearpart and nonlinearpart). */
+enum {
+    FCN_DIFFRACTION = 1, /* (i/2k0)(d2/dr2 + (1/r) d/dr) of Eq. linearpart */
+    FCN_GVD = 2,         /* -(i k''/2) d2/dt2 of Eq. linearpart */
+    FCN_KERR = 4,        /* i (k0/n0) sum_j n_2j |A|^2j of Eq. nonlinearpart */
+    FCN_PLASMA = 8,      /* -(i k0/2) omega_pe^2/omega0^2 = -(i k0/2) rho/rho_c */
+    FCN_MPA = 16,        /* -(beta_K/2) |A|^(2K-2), beta_K = K hbar omega0 sigma_K rho_at */
+    FCN_COLL = 32        /* -(sigma_c/2) rho, collisional absorption (not in the paper) */
+};
+
+enum { FCN_FP64 = 0, FCN_FP32 = 1 };
+
+/* One pulse and its grid. */
+typedef struct {
+    int32_t nr;              /* radial points, 3 <= nr <= 2048; row nr-1 is r = r_max (A = 0) */
+    int32_t nt;              /* time points, a power of two in [256, 8192] */
+    double r_max;            /* [m] */
+    double t_min, t_max;     /* [s]; periodic window, t_max excluded */
+    double lambda0;          /* carrier wavelength [m] */
+    double n0;               /* linear refractive index */
+    double k2;               /* k'' [s^2/m] */
+    double n2, n4, n6, n8;   /* Kerr indices [m^2/W], [m^4/W^2], [m^6/W^3], [m^8/W^4] */
+    int32_t K;               /* photons for multiphoton ionisation, 1 <= K <= 16 */
+    double sigma_K;          /* [s^-1 (m^2/W)^K] */
+    double rho_at;           /* neutral density [m^-3] */
+    double sigma_c;          /* collisional cross-section [m^2] */
+    double dz;               /* step length [m] (fixed mode), ignored when adaptive */
+    uint32_t terms;          /* OR of the FCN_* term switches */
+} fcn_instance;
+
+typedef struct {
+    int32_t precision;       /* FCN_FP64, or FCN_FP32 (field, FFT, CN and exponentials in FP32;
+                                density scan, operator exponents and diagnostics in FP64) */
+    int32_t adaptive;        /* 0: fixed dz per instance; 1: dz_n = clamp(max_phase/Phi, dz_min,
+                                dz_max) with Phi the peak nonlinear phase rate of A^{n-1} */
+    double max_phase;        /* [rad] per step, adaptive mode */
+    double dz_min, dz_max;   /* [m], adaptive mode */
+    int32_t use_graph;       /* 1: replay the step body as a captured HIP graph */
+    int32_t col_tile;        /* 0: auto; else frequencies per column workgroup (8, 16 or 32) */
+    int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (8 or 16) */
+    int32_t reserved;
+} fcn_options;
+
+/* Number of doubles per instance in one diagnostics record: 8 scalars then nr fluence values.
+ * Scalars: [0] energy 2 pi dr^2 dtau (sum_p |A_0p|^2 / 8 + sum_m m sum_p |A_mp|^2) [J],
+ * [1] peak intensity, [2] on-axis peak intensity [W/m^2], [3] peak electron density [m^-3],
+ * [4] peak nonlinear phase rate Phi [rad/m], [5] z [m], [6] step index, [7] dz of the next step;
+ * then fluence F(r_m) = dtau sum_p |A_mp|^2 [J/m^2] for m < nr. */
+#define FCN_DIAG_SCALARS 8
+
+/* Validates the instances and options and builds the host-side plan (derived constants,
+ * twiddle tables, work lists).  inst: host array of `batch` instances (batch >= 1), copied.
+ * opt may be NULL (defaults: FP64, fixed dz, no graph, automatic tiles).
+ * Errors: FCN_E_ARG for invalid values, FCN_E_SIZE for grids outside the supported range. */
+fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_options *opt,
+                           fcn_plan_t *out);
+
+/* Bytes of device workspace the plan needs. */
+fcn_status fcn_plan_workspace_size(fcn_plan_t plan, size_t *bytes);
+
+/* Complex elements of the flat field buffer, and the element offset of instance i in it. */
+fcn_status fcn_field_size(fcn_plan_t plan, size_t *elems);
+fcn_status fcn_field_offset(fcn_plan_t plan, int32_t instance, size_t *elem_offset);
+
+/* Doubles of one diagnostics record for the whole batch: sum_i (FCN_DIAG_SCALARS + nr_i). */
+fcn_status fcn_diag_record_size(fcn_plan_t plan, size_t *doubles);
+
+/* Attaches caller-owned device memory (workspace_dev, at least fcn_plan_workspace_size bytes,
+ * 256-byte aligned) and a HIP stream (hipStream_t cast to void*, NULL = default stream).
+ * Uploads the plan tables on that stream.  May be called again to move the plan to another
+ * workspace or stream; the step counter then restarts at 0. */
+fcn_status fcn_plan_bind(fcn_plan_t plan, void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* Advances every instance by nsteps Strang steps (Sec. 3, Eq. nlseq):
+ * A^{n+1} = NL(dz_n/2) o Linear(dz_n) o NL(dz_n/2) A^n, in place on field_dev.
+ * The linear part is the forward FFT of every row, the Crank-Nicholson solve of every
+ * frequency column (Eqs. matrix-matrix1, with c_j and f_j using (1 + 1/2j)) and the inverse
+ * FFT (Eq. antifourier); the nonlinear half step integrates the electron density along t by
+ * RK4 (Eq. ionization) from rho = 0 at t_min and multiplies by exp(dz/2 N) (Eqs. Anhalf,
+ * Anhalf1, nonlinearpart).  nsteps >= 0.  Errors: FCN_E_STATE before bind. */
+fcn_status fcn_step(fcn_plan_t plan, void *field_dev, int64_t nsteps);
+
+/* Like fcn_step, plus: when diag_dev != NULL and diag_every > 0, writes one diagnostics
+ * record (fcn_diag_record_size doubles) of the state A^n for n = 0, diag_every, 2 diag_every,
+ * ... <= nsteps into diag_dev (records consecutive; the caller sizes it to
+ * (nsteps/diag_every + 1) records).  dz_log_dev: NULL, or a device array of nsteps * batch
+ * doubles; in adaptive mode it receives dz_n of instance i at [n * batch + i]; in fixed mode
+ * with replay = 1 it supplies them instead (the FP32 run replays the FP64 run's steps). */
+fcn_status fcn_propagate(fcn_plan_t plan, void *field_dev, int64_t nsteps, double *diag_dev,
+                         int32_t diag_every, double *dz_log_dev, int32_t replay);
+
+/* One diagnostics record of the current state (no step). */
+fcn_status fcn_diagnostics(fcn_plan_t plan, const void *field_dev, double *diag_dev);
+
+/* Single stages of the step, for tests of each kernel against the CPU oracle.
+ * FCN_STAGE_FFT: forward FFT of every row (unnormalised, exp(-i omega t)).
+ * FCN_STAGE_IFFT: inverse FFT of every row, scaled by 1/nt.
+ * FCN_STAGE_CN: Crank-Nicholson solve of every frequency column over length `length`
+ *   (field in the frequency domain).
+ * FCN_STAGE_NL: one nonlinear sub-step A <- A exp(length N) (length = dz/2 for a half step). */
+enum { FCN_STAGE_FFT = 0, FCN_STAGE_IFFT = 1, FCN_STAGE_CN = 2, FCN_STAGE_NL = 3 };
+fcn_status fcn_stage(fcn_plan_t plan, int32_t stage, void *field_dev, double length);
+
+/* Waits for the bound stream; returns FCN_E_NONFINITE if the device flagged a non-finite
+ * intensity since bind (the flag is then cleared). */
+fcn_status fcn_sync(fcn_plan_t plan);
+
+/* Text of the last error on this plan (valid until the next call on it); "" if none. */
+const char *fcn_last_error(fcn_plan_t plan);
+
+/* Releases the host-side plan.  Device buffers stay owned by the caller. */
+fcn_status fcn_plan_destroy(fcn_plan_t plan);
+
+/* fcn_step with a HIP event recorded on the bound stream between every pass of the steady
+ * steps; waits for the stream, then returns the mean duration [ms] of the fused row pass
+ * (iFFT, two nonlinear half steps, FFT) and of the column pass (CN solve), and the total
+ * elapsed time of the call.  For kernel timing; 2 <= nsteps <= 100000. */
+fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, double *row_ms, double *col_ms,
+                          double *total_ms);
+
+/* Launch configuration the plan chose: rows per thread and frequencies per workgroup of the
+ * column solve, elements per thread of the row kernel. */
+fcn_status fcn_plan_tiles(fcn_plan_t plan, int32_t *col_tile, int32_t *col_rows, int32_t *row_elems);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCN_H */

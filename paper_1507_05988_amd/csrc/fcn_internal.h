@@ -1,0 +1,126 @@
+// fcn_internal.h -- device-side plan layout shared by the kernels and the host runtime of
+// the FCN library.  Not part of the public ABI (include/fcn.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fcn {
+
+// Scalars at the head of each instance's diagnostics record (FCN_DIAG_SCALARS in fcn.h).
+constexpr int DIAG_SCALARS = 8;
+
+// Per-instance constants, computed once on the host in FP64 and uploaded with the plan.
+// The operator coefficients are pre-multiplied so a kernel needs no division:
+//   s_n     = dz_n * diff_unit          the CN off-diagonal scale dz/(4 k0 dr^2)
+//   gamma_p = q_p^2 * dz_n * gvd_unit   the CN GVD term k'' omega_p^2 dz / 4
+//   Im N    = I (ck1 + I (ck2 + I (ck3 + I ck4))) + c_plasma rho
+//   Re N    = c_mpa I^(K-1) + c_coll rho
+struct DevInst {
+    int32_t nr, nt;
+    int64_t field_off;      // complex elements from the start of the field buffer
+    int32_t row_base;       // first global row index (row diagnostics partials)
+    int32_t diag_off;       // double offset of this instance in a diagnostics record
+    int32_t rowcoef_off;    // offset (in rows) of this instance's (1 -+ 1/2m) table
+    int32_t tw_off;         // complex offset of the twiddle table for nt
+    uint32_t terms;
+    int32_t K;
+    double dz_fixed;
+    double diff_unit;       // 1/(4 k0 dr^2), 0 when diffraction is off
+    double gvd_unit;        // k'' (2 pi/(nt dtau))^2 / 4, 0 when GVD is off
+    double dtau, dr;
+    double ck1, ck2, ck3, ck4;  // (k0/n0) n_2j, 0 when Kerr is off
+    double c_plasma;        // -k0/(2 rho_c), 0 when the plasma term is off
+    double c_mpa;           // -beta_K/2, 0 when MPA is off
+    double c_coll;          // -sigma_c/2, 0 when collisional absorption is off
+    double sigma_K, rho_at; // density source sigma_K I^K (rho_at - rho)
+    double need_rho;        // 1 if the density enters N (plasma or collisional)
+    double phi_kerr;        // 1 if the Kerr rate enters Phi
+    double phi_plasma;      // k0/(2 rho_c) if the plasma rate enters Phi, else 0
+    double pad0;
+};
+
+// Mutable device state, one per plan, inside the workspace.
+struct DevState {
+    int64_t cnt_col;        // step index read by the column kernels
+    int64_t cnt_row;        // step index read by the row kernels
+    int32_t nonfinite;      // set to 1 when a non-finite intensity is seen
+    int32_t pad;
+    double z_pad[5];
+};
+
+// Work item of the row pass: one (instance, row).
+struct RowItem {
+    int32_t inst;
+    int32_t m;
+};
+
+// Work item of the column pass: W frequencies [p0, p0+W) of one instance.
+struct ColItem {
+    int32_t inst;
+    int32_t p0;
+};
+
+// Row-kernel stage flags (compile-time).
+enum : int {
+    RK_IFFT_IN = 1,     // input is a spectrum: inverse FFT (with 1/nt) first
+    RK_NL_A = 2,        // nonlinear half step with dz_{n-1}
+    RK_DIAG = 4,        // diagnostics of the state after RK_NL_A (A^n)
+    RK_NL_B = 8,        // nonlinear half step with dz_n
+    RK_FFT_OUT = 16,    // forward FFT, write the spectrum
+    RK_STORE = 32,      // write the row back (time domain unless RK_FFT_OUT)
+    RK_STAGE_LEN = 64,  // stage test: NL_B uses the explicit length argument as its exponent
+};
+
+// Step-length source of a row kernel.
+enum : int { DZ_FIXED = 0, DZ_ADAPTIVE = 1, DZ_REPLAY = 2 };
+
+// Arguments common to the row-kernel launches.
+struct RowArgs {
+    const DevInst *inst;
+    const RowItem *items;
+    int32_t nitems;
+    int32_t batch;
+    void *field;
+    const void *twiddle;      // complex table base (precision of the kernel)
+    double *row_diag;         // [global row][4]: sum I, max I, max rho, max Phi
+    unsigned long long *phi_slot;  // [2][batch] bit patterns of non-negative doubles
+    double *dz_ring;          // [2][batch]
+    double *dz_log;           // [n][batch] or null
+    DevState *state;
+    int32_t dz_mode;
+    int32_t log_dz;           // adaptive: write dz_n to dz_log
+    int32_t seed_slots;       // also write Phi into the lagged slot (first pass after reset)
+    int32_t pad;
+    int64_t log_base;         // step index of dz_log[0]
+    double max_phase, dz_min, dz_max;
+    double stage_len;         // RK_STAGE_LEN
+};
+
+struct ColArgs {
+    const DevInst *inst;
+    const ColItem *items;
+    int32_t nitems;
+    int32_t batch;
+    void *field;
+    const double *rowcoef;    // [row][2]: 1 - 1/(2m), 1 + 1/(2m)
+    double *dz_ring;
+    unsigned long long *phi_slot;
+    double *zpos;
+    DevState *state;
+    int32_t use_stage_len;
+    double stage_len;
+};
+
+// Launchers (defined in the kernel translation units).
+hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid,
+                      hipStream_t s);
+hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s);
+int row_rows_per_group(int nt, int elems);
+hipError_t launch_finalize(const DevInst *inst, int batch, const double *row_diag, const double *zpos,
+                           const double *dz_ring, const DevState *state, double *out, hipStream_t s);
+hipError_t launch_init_state(DevState *state, unsigned long long *phi_slot, double *dz_ring, double *zpos,
+                             int batch, int64_t n0, hipStream_t s);
+hipError_t launch_clear_flag(DevState *state, hipStream_t s);
+
+}  // namespace fcn

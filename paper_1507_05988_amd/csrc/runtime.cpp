@@ -1,0 +1,751 @@
+// runtime.cpp -- host side of the FCN library: plan construction, workspace layout, the
+// step schedule and the C ABI declared in include/fcn.h.
+//
+// Step schedule (Sec. 3 summary, re-organised as in Sec. 4): a call advancing nsteps runs
+//   row pass  [NL(dz_n0/2), diagnostics of A^n0, FFT]
+//   nsteps x ( column pass [CN solve with dz_n]
+//              row pass    [iFFT, NL(dz_n/2) -> A^{n+1}, diagnostics, NL(dz_{n+1}/2), FFT] )
+// where the last row pass stops after the diagnostics and writes the time-domain field.
+// Row passes are launched once per distinct nt (templated FFT), column passes once per
+// distinct nr (workgroup size W * ceil(nr/L)); in a batch every launch covers all
+// instances of its bucket.  The step index, the dz ring and the phase-rate slots live in
+// device memory, so the step body is identical from step to step and can be replayed
+// from a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fcn.h"
+#include "fcn_internal.h"
+
+using namespace fcn;
+
+namespace {
+
+constexpr double kC = 299792458.0;
+constexpr double kHbar = 1.054571817e-34;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kRowElems = 8;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct RowBucket {
+    int nt;
+    int item_off, nitems;
+    int grid;
+};
+struct ColBucket {
+    int nr;
+    int w, l;
+    int item_off, nitems;
+};
+
+}  // namespace
+
+struct fcn_plan_s {
+    std::vector<fcn_instance> insts;
+    fcn_options opt{};
+    int batch = 0;
+    int precision = 0;
+    size_t csize = 16;  // bytes per complex element
+
+    std::vector<DevInst> dinst;
+    size_t field_elems = 0;
+    size_t diag_doubles = 0;
+    int total_rows = 0;
+    std::vector<RowItem> row_items;
+    std::vector<ColItem> col_items;
+    std::vector<RowBucket> row_buckets;
+    std::vector<ColBucket> col_buckets;
+    std::vector<double> rowcoef;        // [row][2]
+    std::vector<unsigned char> twiddles;  // complex tables, precision of the plan
+    int col_w = 0, col_l = 0;
+
+    // workspace layout (byte offsets)
+    size_t off_inst = 0, off_rowitems = 0, off_colitems = 0, off_rowcoef = 0, off_tw = 0;
+    size_t off_rowdiag = 0, off_slots = 0, off_ring = 0, off_zpos = 0, off_state = 0, ws_bytes = 0;
+    size_t const_bytes = 0;  // bytes [0, const_bytes) are the uploaded read-only tables
+    std::vector<unsigned char> image;
+
+    unsigned char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    int64_t n_host = 0;     // step index of the field as seen by the host
+    bool seeded = false;    // phase-rate slots hold Phi of the current state's predecessor
+
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0;
+    void *graph_field = nullptr;
+
+    std::string err;
+
+    DevInst *d_inst() const { return reinterpret_cast<DevInst *>(ws + off_inst); }
+    RowItem *d_rowitems() const { return reinterpret_cast<RowItem *>(ws + off_rowitems); }
+    ColItem *d_colitems() const { return reinterpret_cast<ColItem *>(ws + off_colitems); }
+    double *d_rowcoef() const { return reinterpret_cast<double *>(ws + off_rowcoef); }
+    void *d_tw() const { return ws + off_tw; }
+    double *d_rowdiag() const { return reinterpret_cast<double *>(ws + off_rowdiag); }
+    unsigned long long *d_slots() const { return reinterpret_cast<unsigned long long *>(ws + off_slots); }
+    double *d_ring() const { return reinterpret_cast<double *>(ws + off_ring); }
+    double *d_zpos() const { return reinterpret_cast<double *>(ws + off_zpos); }
+    DevState *d_state() const { return reinterpret_cast<DevState *>(ws + off_state); }
+};
+
+namespace {
+
+fcn_status fail(fcn_plan_t p, fcn_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+fcn_status fail(fcn_plan_t p, fcn_status st, const char *fmt, ...) {
+    if (p) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        p->err = buf;
+    }
+    return st;
+}
+
+fcn_status hip_fail(fcn_plan_t p, hipError_t e, const char *what) {
+    return fail(p, FCN_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+const char *check_instance(const fcn_instance &in) {
+    if (in.nr < 3 || in.nr > 2048) return "nr must be in [3, 2048]";
+    if (!is_pow2(in.nt) || in.nt < 64 || in.nt > 8192) return "nt must be a power of two in [64, 8192]";
+    if (!(in.r_max > 0.0) || !std::isfinite(in.r_max)) return "r_max must be positive";
+    if (!(in.t_max > in.t_min) || !std::isfinite(in.t_max) || !std::isfinite(in.t_min)) return "t_max must exceed t_min";
+    if (!(in.lambda0 > 0.0) || !(in.n0 > 0.0)) return "lambda0 and n0 must be positive";
+    if (!std::isfinite(in.k2) || !std::isfinite(in.n2) || !std::isfinite(in.n4) || !std::isfinite(in.n6) ||
+        !std::isfinite(in.n8))
+        return "non-finite dispersion or Kerr coefficient";
+    if (in.K < 1 || in.K > 16) return "K must be in [1, 16]";
+    if (!(in.sigma_K >= 0.0) || !(in.rho_at >= 0.0) || !(in.sigma_c >= 0.0)) return "negative density coefficient";
+    if ((in.terms & ~63u) != 0) return "unknown term bit";
+    if (!(in.dz >= 0.0) || !std::isfinite(in.dz)) return "dz must be finite and non-negative";
+    return nullptr;
+}
+
+// Twiddles W_nt^k = exp(-2 pi i k / nt), k < nt: cos/sin of the reduced angle in FP64,
+// using the octant symmetries so each entry is a correctly reduced evaluation.
+void twiddle_table(int nt, std::vector<double> &re, std::vector<double> &im) {
+    re.resize(nt);
+    im.resize(nt);
+    for (int k = 0; k < nt; k++) {
+        // angle = 2 pi k / nt in [0, 2 pi): reduce to u = k mod (nt/8) style via exact integers
+        const long q8 = (long)k * 8;
+        const int oct = (int)(q8 / nt);          // octant 0..7
+        const long rem = q8 - (long)oct * nt;    // 0 <= rem < nt
+        // theta = (oct + rem/nt) * pi/4
+        double c, s;
+        const double x = (double)rem / (double)nt * (kPi / 4.0);  // in [0, pi/4)
+        const double cx = std::cos(x), sx = std::sin(x);
+        const double cy = std::cos(kPi / 4.0 - x), sy = std::sin(kPi / 4.0 - x);
+        switch (oct) {
+            case 0: c = cx; s = sx; break;
+            case 1: c = sy; s = cy; break;
+            case 2: c = -sx; s = cx; break;
+            case 3: c = -cy; s = sy; break;
+            case 4: c = -cx; s = -sx; break;
+            case 5: c = -sy; s = -cy; break;
+            case 6: c = sx; s = -cx; break;
+            default: c = cy; s = -sy; break;
+        }
+        re[k] = c;
+        im[k] = -s;  // exp(-i theta)
+    }
+}
+
+bool col_tiles_supported(int w, int l) {
+    return (w == 4 && (l == 8 || l == 16)) || (w == 8 && (l == 8 || l == 16)) || (w == 16 && (l == 8 || l == 16)) ||
+           (w == 32 && l == 8);
+}
+
+// Column tile choice: frequencies per workgroup W and rows per thread L.
+void choose_col_tiles(int precision, int nr, const fcn_options &opt, int &w, int &l) {
+    l = opt.col_rows ? opt.col_rows : (precision == 0 ? 8 : 16);
+    w = opt.col_tile ? opt.col_tile : (precision == 0 ? 8 : 16);
+    // keep the workgroup within 512 threads
+    while (w * ((nr + l - 1) / l) > 512 && w > 4) w /= 2;
+    while (w * ((nr + l - 1) / l) > 512 && l < 16) l *= 2;
+}
+
+fcn_status build_plan(fcn_plan_t p) {
+    const int B = p->batch;
+    p->csize = p->precision == 0 ? 16 : 8;
+    p->dinst.resize(B);
+
+    // twiddle tables per distinct nt
+    std::map<int, int> tw_off;
+    size_t tw_elems = 0;
+    for (const auto &in : p->insts)
+        if (!tw_off.count(in.nt)) {
+            tw_off[in.nt] = (int)tw_elems;
+            tw_elems += in.nt;
+        }
+    p->twiddles.assign(tw_elems * p->csize, 0);
+    for (auto &kv : tw_off) {
+        std::vector<double> re, im;
+        twiddle_table(kv.first, re, im);
+        for (int k = 0; k < kv.first; k++) {
+            const size_t e = (size_t)kv.second + k;
+            if (p->precision == 0) {
+                double v[2] = {re[k], im[k]};
+                memcpy(&p->twiddles[e * 16], v, 16);
+            } else {
+                float v[2] = {(float)re[k], (float)im[k]};
+                memcpy(&p->twiddles[e * 8], v, 8);
+            }
+        }
+    }
+
+    // row-coefficient tables per distinct nr
+    std::map<int, int> rc_off;
+    int rc_rows = 0;
+    for (const auto &in : p->insts)
+        if (!rc_off.count(in.nr)) {
+            rc_off[in.nr] = rc_rows;
+            rc_rows += in.nr;
+        }
+    p->rowcoef.assign(2 * (size_t)rc_rows, 0.0);
+    for (auto &kv : rc_off)
+        for (int m = 1; m < kv.first; m++) {
+            p->rowcoef[2 * ((size_t)kv.second + m)] = 1.0 - 1.0 / (2.0 * m);
+            p->rowcoef[2 * ((size_t)kv.second + m) + 1] = 1.0 + 1.0 / (2.0 * m);
+        }
+
+    // per-instance constants and offsets
+    size_t off = 0;
+    int row = 0;
+    size_t doff = 0;
+    for (int i = 0; i < B; i++) {
+        const fcn_instance &in = p->insts[i];
+        DevInst d{};
+        d.nr = in.nr;
+        d.nt = in.nt;
+        d.field_off = (int64_t)off;
+        d.row_base = row;
+        d.diag_off = (int)doff;
+        d.rowcoef_off = rc_off[in.nr];
+        d.tw_off = tw_off[in.nt];
+        d.terms = in.terms;
+        d.K = in.K;
+        d.dz_fixed = in.dz;
+        const double k0 = 2.0 * kPi * in.n0 / in.lambda0;
+        const double w0 = 2.0 * kPi * kC / in.lambda0;
+        const double rho_c = kEps0 * kMe * w0 * w0 / (kQe * kQe);
+        const double beta = (double)in.K * kHbar * w0 * in.sigma_K * in.rho_at;
+        d.dr = in.r_max / (double)(in.nr - 1);
+        d.dtau = (in.t_max - in.t_min) / (double)in.nt;
+        d.diff_unit = (in.terms & FCN_DIFFRACTION) ? 1.0 / (4.0 * k0 * d.dr * d.dr) : 0.0;
+        const double wu = 2.0 * kPi / ((double)in.nt * d.dtau);
+        d.gvd_unit = (in.terms & FCN_GVD) ? in.k2 * wu * wu / 4.0 : 0.0;
+        const bool kerr = (in.terms & FCN_KERR) != 0;
+        d.ck1 = kerr ? k0 / in.n0 * in.n2 : 0.0;
+        d.ck2 = kerr ? k0 / in.n0 * in.n4 : 0.0;
+        d.ck3 = kerr ? k0 / in.n0 * in.n6 : 0.0;
+        d.ck4 = kerr ? k0 / in.n0 * in.n8 : 0.0;
+        d.c_plasma = (in.terms & FCN_PLASMA) ? -k0 / (2.0 * rho_c) : 0.0;
+        d.c_mpa = (in.terms & FCN_MPA) ? -beta / 2.0 : 0.0;
+        d.c_coll = (in.terms & FCN_COLL) ? -in.sigma_c / 2.0 : 0.0;
+        d.sigma_K = in.sigma_K;
+        d.rho_at = in.rho_at;
+        d.need_rho = ((in.terms & (FCN_PLASMA | FCN_COLL)) != 0 && in.rho_at > 0.0 && in.sigma_K > 0.0) ? 1.0 : 0.0;
+        d.phi_kerr = kerr ? 1.0 : 0.0;
+        d.phi_plasma = (in.terms & FCN_PLASMA) ? k0 / (2.0 * rho_c) : 0.0;
+        p->dinst[i] = d;
+        off += (size_t)in.nr * in.nt;
+        row += in.nr;
+        doff += DIAG_SCALARS + in.nr;
+    }
+    p->field_elems = off;
+    p->total_rows = row;
+    p->diag_doubles = doff;
+
+    // row work lists, one bucket per nt
+    std::map<int, std::vector<int>> by_nt;
+    for (int i = 0; i < B; i++) by_nt[p->insts[i].nt].push_back(i);
+    for (auto &kv : by_nt) {
+        RowBucket b{};
+        b.nt = kv.first;
+        b.item_off = (int)p->row_items.size();
+        for (int i : kv.second)
+            for (int m = 0; m < p->insts[i].nr; m++) p->row_items.push_back(RowItem{i, m});
+        b.nitems = (int)p->row_items.size() - b.item_off;
+        const int rpw = row_rows_per_group(b.nt, kRowElems);
+        b.grid = (b.nitems + rpw - 1) / rpw;
+        p->row_buckets.push_back(b);
+    }
+    // column work lists, one bucket per nr
+    std::map<int, std::vector<int>> by_nr;
+    for (int i = 0; i < B; i++) by_nr[p->insts[i].nr].push_back(i);
+    for (auto &kv : by_nr) {
+        ColBucket b{};
+        b.nr = kv.first;
+        choose_col_tiles(p->precision, b.nr, p->opt, b.w, b.l);
+        if (b.w * ((b.nr + b.l - 1) / b.l) > 512) return fail(p, FCN_E_SIZE, "nr=%d too large for the column solve", b.nr);
+        if (!col_tiles_supported(b.w, b.l)) return fail(p, FCN_E_ARG, "column tile %dx%d not built", b.w, b.l);
+        b.item_off = (int)p->col_items.size();
+        for (int i : kv.second)
+            for (int p0 = 0; p0 < p->insts[i].nt; p0 += b.w) p->col_items.push_back(ColItem{i, p0});
+        b.nitems = (int)p->col_items.size() - b.item_off;
+        p->col_buckets.push_back(b);
+        p->col_w = b.w;
+        p->col_l = b.l;
+    }
+
+    // workspace layout
+    size_t o = 0;
+    p->off_inst = o;
+    o = align_up(o + sizeof(DevInst) * B, 256);
+    p->off_rowitems = o;
+    o = align_up(o + sizeof(RowItem) * p->row_items.size(), 256);
+    p->off_colitems = o;
+    o = align_up(o + sizeof(ColItem) * p->col_items.size(), 256);
+    p->off_rowcoef = o;
+    o = align_up(o + sizeof(double) * p->rowcoef.size(), 256);
+    p->off_tw = o;
+    o = align_up(o + p->twiddles.size(), 256);
+    p->const_bytes = o;
+    p->off_rowdiag = o;
+    o = align_up(o + sizeof(double) * 4 * (size_t)p->total_rows, 256);
+    p->off_slots = o;
+    o = align_up(o + sizeof(unsigned long long) * 2 * B, 256);
+    p->off_ring = o;
+    o = align_up(o + sizeof(double) * 2 * B, 256);
+    p->off_zpos = o;
+    o = align_up(o + sizeof(double) * B, 256);
+    p->off_state = o;
+    o = align_up(o + sizeof(DevState), 256);
+    p->ws_bytes = o;
+
+    p->image.assign(p->const_bytes, 0);
+    memcpy(&p->image[p->off_inst], p->dinst.data(), sizeof(DevInst) * B);
+    memcpy(&p->image[p->off_rowitems], p->row_items.data(), sizeof(RowItem) * p->row_items.size());
+    memcpy(&p->image[p->off_colitems], p->col_items.data(), sizeof(ColItem) * p->col_items.size());
+    memcpy(&p->image[p->off_rowcoef], p->rowcoef.data(), sizeof(double) * p->rowcoef.size());
+    memcpy(&p->image[p->off_tw], p->twiddles.data(), p->twiddles.size());
+    return FCN_OK;
+}
+
+RowArgs row_args(fcn_plan_t p, void *field, const RowBucket &b) {
+    RowArgs a{};
+    a.inst = p->d_inst();
+    a.items = p->d_rowitems() + b.item_off;
+    a.nitems = b.nitems;
+    a.batch = p->batch;
+    a.field = field;
+    a.twiddle = p->d_tw();
+    a.row_diag = p->d_rowdiag();
+    a.phi_slot = p->d_slots();
+    a.dz_ring = p->d_ring();
+    a.dz_log = nullptr;
+    a.state = p->d_state();
+    a.dz_mode = p->opt.adaptive ? DZ_ADAPTIVE : DZ_FIXED;
+    a.max_phase = p->opt.max_phase;
+    a.dz_min = p->opt.dz_min;
+    a.dz_max = p->opt.dz_max;
+    return a;
+}
+
+ColArgs col_args(fcn_plan_t p, void *field, const ColBucket &b) {
+    ColArgs a{};
+    a.inst = p->d_inst();
+    a.items = p->d_colitems() + b.item_off;
+    a.nitems = b.nitems;
+    a.batch = p->batch;
+    a.field = field;
+    a.rowcoef = p->d_rowcoef();
+    a.dz_ring = p->d_ring();
+    a.phi_slot = p->d_slots();
+    a.zpos = p->d_zpos();
+    a.state = p->d_state();
+    return a;
+}
+
+struct StepCtx {
+    double *dz_log = nullptr;
+    int64_t log_base = 0;
+    int replay = 0;
+};
+
+hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, int seed, double stage_len = 0.0) {
+    for (const auto &b : p->row_buckets) {
+        RowArgs a = row_args(p, field, b);
+        a.dz_log = ctx.dz_log;
+        a.log_base = ctx.log_base;
+        if (ctx.replay && !p->opt.adaptive) a.dz_mode = DZ_REPLAY;
+        a.seed_slots = seed;
+        a.stage_len = stage_len;
+        hipError_t e = launch_row(p->precision, b.nt, kRowElems, flags, a, b.grid, p->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0) {
+    for (const auto &b : p->col_buckets) {
+        ColArgs a = col_args(p, field, b);
+        a.use_stage_len = stage;
+        a.stage_len = stage_len;
+        hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, p->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+constexpr int F_FIRST = RK_NL_B | RK_DIAG | RK_FFT_OUT | RK_STORE;
+constexpr int F_MIDDLE = RK_IFFT_IN | RK_NL_A | RK_DIAG | RK_NL_B | RK_FFT_OUT | RK_STORE;
+constexpr int F_LAST = RK_IFFT_IN | RK_NL_A | RK_DIAG | RK_STORE;
+constexpr int F_DIAG = RK_DIAG;
+
+hipError_t finalize(fcn_plan_t p, double *out) {
+    return launch_finalize(p->d_inst(), p->batch, p->d_rowdiag(), p->d_zpos(), p->d_ring(), p->d_state(), out,
+                           p->stream);
+}
+
+// Captures `steps` step bodies (column pass + middle row pass) into an executable graph.
+fcn_status ensure_graph(fcn_plan_t p, void *field, int steps) {
+    if (p->graph_exec && p->graph_steps == steps) return FCN_OK;
+    if (p->graph_exec) {
+        hipGraphExecDestroy(p->graph_exec);
+        p->graph_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(p, e, "hipStreamBeginCapture");
+    StepCtx ctx;
+    for (int s = 0; s < steps && e == hipSuccess; s++) {
+        e = col_pass(p, field, 0);
+        if (e == hipSuccess) e = row_pass(p, field, F_MIDDLE, ctx, 0);
+    }
+    hipError_t e2 = hipStreamEndCapture(p->stream, &g);
+    if (e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return hip_fail(p, e, "kernel launch during capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(p, e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGraphInstantiate");
+    p->graph_steps = steps;
+    p->graph_field = field;
+    return FCN_OK;
+}
+
+fcn_status run_steps(fcn_plan_t p, void *field, int64_t nsteps, double *diag, int diag_every, double *dz_log,
+                     int replay) {
+    if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
+    if (!field) return fail(p, FCN_E_ARG, "field is NULL");
+    if (nsteps < 0) return fail(p, FCN_E_ARG, "nsteps < 0");
+    if (replay && (!dz_log || p->opt.adaptive)) return fail(p, FCN_E_ARG, "replay needs a dz log and fixed mode");
+    if (nsteps == 0 && !diag) return FCN_OK;
+    StepCtx ctx{dz_log, p->n_host, replay};
+    const bool want_diag = diag != nullptr && diag_every > 0;
+    int64_t rec = 0;
+    hipError_t e = hipSuccess;
+    // Adaptive mode: Phi of the state before the first step seeds both slots (dz_0 from A^0).
+    if (p->opt.adaptive && !p->seeded) {
+        e = row_pass(p, field, F_DIAG, ctx, 1);
+        if (e != hipSuccess) return hip_fail(p, e, "diagnostics pass");
+        p->seeded = true;
+    }
+    if (nsteps == 0) {
+        e = row_pass(p, field, F_DIAG, ctx, 0);
+        if (e == hipSuccess && want_diag) e = finalize(p, diag);
+        return e == hipSuccess ? FCN_OK : hip_fail(p, e, "diagnostics");
+    }
+    e = row_pass(p, field, F_FIRST, ctx, 0);
+    if (e != hipSuccess) return hip_fail(p, e, "row pass");
+    if (want_diag) {
+        e = finalize(p, diag + (rec++) * p->diag_doubles);
+        if (e != hipSuccess) return hip_fail(p, e, "finalize");
+    }
+    // graphs need a capturable (non-default) stream; they hold the field pointer
+    const bool graph_ok = p->opt.use_graph && !want_diag && p->stream != nullptr;
+    if (graph_ok && p->graph_exec && p->graph_field != field) {
+        hipGraphExecDestroy(p->graph_exec);
+        p->graph_exec = nullptr;
+        p->graph_steps = 0;
+    }
+    int64_t s = 0;
+    // middle steps: s = 0 .. nsteps-2 end with a middle row pass (state A^{n0+s+1})
+    while (s < nsteps - 1) {
+        int64_t chunk = 1;
+        if (graph_ok) {
+            const int gs = 16;
+            if (nsteps - 1 - s >= gs) {
+                fcn_status st = ensure_graph(p, field, gs);
+                if (st != FCN_OK) return st;
+                e = hipGraphLaunch(p->graph_exec, p->stream);
+                if (e != hipSuccess) return hip_fail(p, e, "hipGraphLaunch");
+                s += gs;
+                continue;
+            }
+        }
+        e = col_pass(p, field, 0);
+        if (e == hipSuccess) e = row_pass(p, field, F_MIDDLE, ctx, 0);
+        if (e != hipSuccess) return hip_fail(p, e, "step");
+        s += chunk;
+        if (want_diag && s % diag_every == 0) {
+            e = finalize(p, diag + (rec++) * p->diag_doubles);
+            if (e != hipSuccess) return hip_fail(p, e, "finalize");
+        }
+    }
+    e = col_pass(p, field, 0);
+    if (e == hipSuccess) e = row_pass(p, field, F_LAST, ctx, 0);
+    if (e != hipSuccess) return hip_fail(p, e, "last step");
+    p->n_host += nsteps;
+    if (want_diag && nsteps % diag_every == 0) {
+        e = finalize(p, diag + (rec++) * p->diag_doubles);
+        if (e != hipSuccess) return hip_fail(p, e, "finalize");
+    }
+    return FCN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_options *opt, fcn_plan_t *out) {
+    if (!out) return FCN_E_ARG;
+    *out = nullptr;
+    if (!inst || batch < 1) return FCN_E_ARG;
+    fcn_plan_t p = new fcn_plan_s();
+    p->batch = batch;
+    p->insts.assign(inst, inst + batch);
+    if (opt) p->opt = *opt;
+    p->precision = p->opt.precision;
+    if (p->precision != FCN_FP64 && p->precision != FCN_FP32) {
+        delete p;
+        return FCN_E_ARG;
+    }
+    if (p->opt.adaptive) {
+        if (!(p->opt.max_phase > 0.0) || !(p->opt.dz_min > 0.0) || !(p->opt.dz_max >= p->opt.dz_min)) {
+            delete p;
+            return FCN_E_ARG;
+        }
+    }
+    if (p->opt.col_tile && p->opt.col_tile != 4 && p->opt.col_tile != 8 && p->opt.col_tile != 16 &&
+        p->opt.col_tile != 32) {
+        delete p;
+        return FCN_E_ARG;
+    }
+    if (p->opt.col_rows && p->opt.col_rows != 8 && p->opt.col_rows != 16) {
+        delete p;
+        return FCN_E_ARG;
+    }
+    for (int i = 0; i < batch; i++) {
+        const char *why = check_instance(inst[i]);
+        if (why) {
+            delete p;
+            return (inst[i].nr > 2048 || inst[i].nt > 8192) ? FCN_E_SIZE : FCN_E_ARG;
+        }
+        if (!p->opt.adaptive && !(inst[i].dz > 0.0)) {
+            delete p;
+            return FCN_E_ARG;
+        }
+    }
+    fcn_status st = build_plan(p);
+    if (st != FCN_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return FCN_OK;
+}
+
+fcn_status fcn_plan_workspace_size(fcn_plan_t p, size_t *bytes) {
+    if (!p || !bytes) return FCN_E_ARG;
+    *bytes = p->ws_bytes;
+    return FCN_OK;
+}
+
+fcn_status fcn_field_size(fcn_plan_t p, size_t *elems) {
+    if (!p || !elems) return FCN_E_ARG;
+    *elems = p->field_elems;
+    return FCN_OK;
+}
+
+fcn_status fcn_field_offset(fcn_plan_t p, int32_t instance, size_t *elem_offset) {
+    if (!p || !elem_offset) return FCN_E_ARG;
+    if (instance < 0 || instance >= p->batch) return fail(p, FCN_E_ARG, "instance %d out of range", instance);
+    *elem_offset = (size_t)p->dinst[instance].field_off;
+    return FCN_OK;
+}
+
+fcn_status fcn_diag_record_size(fcn_plan_t p, size_t *doubles) {
+    if (!p || !doubles) return FCN_E_ARG;
+    *doubles = p->diag_doubles;
+    return FCN_OK;
+}
+
+fcn_status fcn_plan_tiles(fcn_plan_t p, int32_t *col_tile, int32_t *col_rows, int32_t *row_elems) {
+    if (!p) return FCN_E_ARG;
+    if (col_tile) *col_tile = p->col_w;
+    if (col_rows) *col_rows = p->col_l;
+    if (row_elems) *row_elems = kRowElems;
+    return FCN_OK;
+}
+
+fcn_status fcn_plan_bind(fcn_plan_t p, void *workspace_dev, size_t workspace_bytes, void *stream) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    if (!workspace_dev) return fail(p, FCN_E_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(p, FCN_E_ARG, "workspace must be 256-byte aligned");
+    if (workspace_bytes < p->ws_bytes)
+        return fail(p, FCN_E_SIZE, "workspace has %zu bytes, plan needs %zu", workspace_bytes, p->ws_bytes);
+    if (p->graph_exec) {
+        hipGraphExecDestroy(p->graph_exec);
+        p->graph_exec = nullptr;
+        p->graph_steps = 0;
+    }
+    p->ws = static_cast<unsigned char *>(workspace_dev);
+    p->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(p->ws, p->image.data(), p->const_bytes, hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(p, e, "upload plan tables");
+    e = launch_init_state(p->d_state(), p->d_slots(), p->d_ring(), p->d_zpos(), p->batch, 0, p->stream);
+    if (e != hipSuccess) return hip_fail(p, e, "init state");
+    // the host image must stay alive until the copy has run
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(p, e, "hipStreamSynchronize");
+    p->bound = true;
+    p->n_host = 0;
+    p->seeded = false;
+    return FCN_OK;
+}
+
+fcn_status fcn_step(fcn_plan_t p, void *field_dev, int64_t nsteps) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    return run_steps(p, field_dev, nsteps, nullptr, 0, nullptr, 0);
+}
+
+fcn_status fcn_propagate(fcn_plan_t p, void *field_dev, int64_t nsteps, double *diag_dev, int32_t diag_every,
+                         double *dz_log_dev, int32_t replay) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    if (diag_dev && diag_every <= 0) return fail(p, FCN_E_ARG, "diag_every must be positive with a diag buffer");
+    return run_steps(p, field_dev, nsteps, diag_dev, diag_every, dz_log_dev, replay);
+}
+
+fcn_status fcn_diagnostics(fcn_plan_t p, const void *field_dev, double *diag_dev) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
+    if (!field_dev || !diag_dev) return fail(p, FCN_E_ARG, "NULL buffer");
+    StepCtx ctx;
+    hipError_t e = row_pass(p, const_cast<void *>(field_dev), F_DIAG, ctx, 0);
+    if (e == hipSuccess) e = finalize(p, diag_dev);
+    return e == hipSuccess ? FCN_OK : hip_fail(p, e, "diagnostics");
+}
+
+fcn_status fcn_stage(fcn_plan_t p, int32_t stage, void *field_dev, double length) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
+    if (!field_dev) return fail(p, FCN_E_ARG, "field is NULL");
+    if (!std::isfinite(length)) return fail(p, FCN_E_ARG, "length must be finite");
+    StepCtx ctx;
+    hipError_t e;
+    switch (stage) {
+        case FCN_STAGE_FFT: e = row_pass(p, field_dev, RK_FFT_OUT | RK_STORE, ctx, 0); break;
+        case FCN_STAGE_IFFT: e = row_pass(p, field_dev, RK_IFFT_IN | RK_STORE, ctx, 0); break;
+        case FCN_STAGE_NL: e = row_pass(p, field_dev, RK_NL_B | RK_STORE | RK_STAGE_LEN, ctx, 0, length); break;
+        case FCN_STAGE_CN: e = col_pass(p, field_dev, 1, length); break;
+        default: return fail(p, FCN_E_ARG, "unknown stage %d", stage);
+    }
+    return e == hipSuccess ? FCN_OK : hip_fail(p, e, "stage");
+}
+
+fcn_status fcn_sync(fcn_plan_t p) {
+    if (!p) return FCN_E_ARG;
+    if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(p, e, "hipStreamSynchronize");
+    int32_t flag = 0;
+    e = hipMemcpy(&flag, &p->d_state()->nonfinite, sizeof flag, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(p, e, "read flag");
+    if (flag) {
+        e = launch_clear_flag(p->d_state(), p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        return fail(p, FCN_E_NONFINITE, "non-finite intensity in the field");
+    }
+    return FCN_OK;
+}
+
+fcn_status fcn_step_timed(fcn_plan_t p, void *field_dev, int64_t nsteps, double *row_ms, double *col_ms,
+                          double *total_ms) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
+    if (!field_dev || !row_ms || !col_ms || !total_ms) return fail(p, FCN_E_ARG, "NULL argument");
+    if (nsteps < 2 || nsteps > 100000) return fail(p, FCN_E_ARG, "nsteps must be in [2, 100000]");
+    // Steady steps s = 0 .. mid-1 each run a column pass then a fused row pass.
+    // ev[0]: start; ev[1]: after the first row pass; ev[2s+2]: after column pass s;
+    // ev[2s+3]: after row pass s; ev[2 mid + 2]: after the closing passes.
+    const int64_t mid = nsteps - 1;
+    std::vector<hipEvent_t> ev((size_t)(2 * mid + 3), nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    StepCtx ctx;
+    if (e == hipSuccess && p->opt.adaptive && !p->seeded) {
+        e = row_pass(p, field_dev, F_DIAG, ctx, 1);
+        p->seeded = true;
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[0], p->stream);
+    if (e == hipSuccess) e = row_pass(p, field_dev, F_FIRST, ctx, 0);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
+    for (int64_t s = 0; s < mid && e == hipSuccess; s++) {
+        e = col_pass(p, field_dev, 0);
+        if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 2], p->stream);
+        if (e == hipSuccess) e = row_pass(p, field_dev, F_MIDDLE, ctx, 0);
+        if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 3], p->stream);
+    }
+    if (e == hipSuccess) e = col_pass(p, field_dev, 0);
+    if (e == hipSuccess) e = row_pass(p, field_dev, F_LAST, ctx, 0);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * mid + 2], p->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * mid + 2]);
+    double rsum = 0.0, csum = 0.0;
+    float tot = 0.f;
+    for (int64_t s = 0; s < mid && e == hipSuccess; s++) {
+        float c = 0.f, r = 0.f;
+        e = hipEventElapsedTime(&c, ev[2 * s + 1], ev[2 * s + 2]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&r, ev[2 * s + 2], ev[2 * s + 3]);
+        csum += c;
+        rsum += r;
+    }
+    if (e == hipSuccess) e = hipEventElapsedTime(&tot, ev[0], ev[2 * mid + 2]);
+    for (auto &x : ev)
+        if (x) hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(p, e, "timed step");
+    p->n_host += nsteps;
+    *col_ms = csum / (double)mid;
+    *row_ms = rsum / (double)mid;
+    *total_ms = tot;
+    return FCN_OK;
+}
+
+const char *fcn_last_error(fcn_plan_t p) { return p ? p->err.c_str() : "NULL plan"; }
+
+fcn_status fcn_plan_destroy(fcn_plan_t p) {
+    if (!p) return FCN_E_ARG;
+    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+    delete p;
+    return FCN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,257 @@
+"""Python binding of the C ABI in include/fcn.h (argument marshalling only).
+
+Every step of the z-step runs in the HIP kernels of libfcn.so; this module only packs
+arguments, allocates device buffers with torch and passes raw pointers and the current
+torch stream.  There is no CPU fallback: without the built library (or without a GPU)
+every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfcn.so")
+
+FCN_OK, FCN_E_ARG, FCN_E_SIZE, FCN_E_HIP, FCN_E_NONFINITE, FCN_E_STATE, FCN_E_UNSUPPORTED = range(7)
+FCN_FP64, FCN_FP32 = 0, 1
+STAGE_FFT, STAGE_IFFT, STAGE_CN, STAGE_NL = 0, 1, 2, 3
+DIAG_SCALARS = 8
+DIAG_NAMES = ("energy", "i_max", "i_axis", "rho_max", "phi", "z", "step", "dz_prev")
+
+EXPORTED = (
+    "fcn_plan_create", "fcn_plan_workspace_size", "fcn_field_size", "fcn_field_offset",
+    "fcn_diag_record_size", "fcn_plan_bind", "fcn_step", "fcn_propagate", "fcn_diagnostics",
+    "fcn_stage", "fcn_sync", "fcn_last_error", "fcn_plan_destroy", "fcn_plan_tiles", "fcn_step_timed",
+)
+
+
+class FcnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"FCN error {code}: {msg}")
+        self.code = code
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("nr", ctypes.c_int32), ("nt", ctypes.c_int32),
+        ("r_max", ctypes.c_double), ("t_min", ctypes.c_double), ("t_max", ctypes.c_double),
+        ("lambda0", ctypes.c_double), ("n0", ctypes.c_double), ("k2", ctypes.c_double),
+        ("n2", ctypes.c_double), ("n4", ctypes.c_double), ("n6", ctypes.c_double), ("n8", ctypes.c_double),
+        ("K", ctypes.c_int32),
+        ("sigma_K", ctypes.c_double), ("rho_at", ctypes.c_double), ("sigma_c", ctypes.c_double),
+        ("dz", ctypes.c_double),
+        ("terms", ctypes.c_uint32),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32),
+        ("max_phase", ctypes.c_double), ("dz_min", ctypes.c_double), ("dz_max", ctypes.c_double),
+        ("use_graph", ctypes.c_int32), ("col_tile", ctypes.c_int32), ("col_rows", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfcn.so and declare its signatures; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FcnError(FCN_E_STATE, f"{path} is missing: run `python -m paper_1507_05988_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    plan_p = ctypes.POINTER(vp)
+    sig = {
+        "fcn_plan_create": ([ctypes.POINTER(Instance), i32, ctypes.POINTER(Options), plan_p], ctypes.c_int),
+        "fcn_plan_workspace_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcn_field_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcn_field_offset": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcn_diag_record_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcn_plan_bind": ([vp, vp, sz, vp], ctypes.c_int),
+        "fcn_step": ([vp, vp, i64], ctypes.c_int),
+        "fcn_propagate": ([vp, vp, i64, vp, i32, vp, i32], ctypes.c_int),
+        "fcn_diagnostics": ([vp, vp, vp], ctypes.c_int),
+        "fcn_stage": ([vp, i32, vp, dbl], ctypes.c_int),
+        "fcn_sync": ([vp], ctypes.c_int),
+        "fcn_last_error": ([vp], ctypes.c_char_p),
+        "fcn_plan_destroy": ([vp], ctypes.c_int),
+        "fcn_plan_tiles": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "fcn_step_timed": ([vp, vp, i64, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+                           ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def make_instance(inst: dict) -> Instance:
+    c = Instance()
+    for name, _ in Instance._fields_:
+        val = inst[name]
+        setattr(c, name, int(val) if name in ("nr", "nt", "K", "terms") else float(val))
+    return c
+
+
+class Plan:
+    """A batch of pulses stepped together on one GPU.
+
+    instances: list of instance dicts (see workloads.py); precision "fp64" or "fp32".
+    The field is one flat complex torch tensor on the device (complex128 / complex64),
+    instance i occupying [offset(i), offset(i) + nr*nt) as a row-major [nr][nt] matrix.
+    """
+
+    def __init__(self, instances, precision: str = "fp64", adaptive: bool = False, max_phase: float = 0.05,
+                 dz_min: float = 1e-6, dz_max: float = 1e-2, use_graph: bool = False, col_tile: int = 0,
+                 col_rows: int = 0, device: int = 0, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise FcnError(FCN_E_STATE, "no GPU: the FCN library has no CPU path")
+        self.torch = torch
+        self.lib = load_library()
+        if isinstance(instances, dict):
+            instances = [instances]
+        self.instances = [dict(i) for i in instances]
+        self.batch = len(self.instances)
+        self.precision = precision
+        self.device = torch.device("cuda", device)
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        arr = (Instance * self.batch)(*[make_instance(i) for i in self.instances])
+        opt = Options(precision=FCN_FP64 if precision == "fp64" else FCN_FP32, adaptive=int(adaptive),
+                      max_phase=max_phase, dz_min=dz_min, dz_max=dz_max, use_graph=int(use_graph),
+                      col_tile=col_tile, col_rows=col_rows, reserved=0)
+        self._h = ctypes.c_void_p()
+        rc = self.lib.fcn_plan_create(arr, self.batch, ctypes.byref(opt), ctypes.byref(self._h))
+        if rc != FCN_OK:
+            raise FcnError(rc, "fcn_plan_create rejected the instances or options")
+        sz = ctypes.c_size_t()
+        self._check(self.lib.fcn_plan_workspace_size(self._h, ctypes.byref(sz)))
+        self.workspace_bytes = sz.value
+        self._check(self.lib.fcn_field_size(self._h, ctypes.byref(sz)))
+        self.field_elems = sz.value
+        self._check(self.lib.fcn_diag_record_size(self._h, ctypes.byref(sz)))
+        self.diag_record = sz.value
+        self.offsets = []
+        for i in range(self.batch):
+            self._check(self.lib.fcn_field_offset(self._h, i, ctypes.byref(sz)))
+            self.offsets.append(sz.value)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            # 256-byte aligned workspace carved from a torch allocation
+            self._ws_buf = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws_buf.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._check(self.lib.fcn_plan_bind(self._h, ctypes.c_void_p(self._ws_ptr), self.workspace_bytes,
+                                           ctypes.c_void_p(self.stream.cuda_stream)))
+
+    # ---------------------------------------------------------------- helpers
+    def _check(self, rc: int):
+        if rc != FCN_OK:
+            msg = self.lib.fcn_last_error(self._h).decode() if self._h else ""
+            raise FcnError(rc, msg)
+
+    def tiles(self):
+        w, l, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.fcn_plan_tiles(self._h, ctypes.byref(w), ctypes.byref(l), ctypes.byref(e)))
+        return w.value, l.value, e.value
+
+    def empty_field(self):
+        return self.torch.zeros(self.field_elems, dtype=self.cdtype, device=self.device)
+
+    def pack(self, fields) -> "torch.Tensor":
+        """List of [nr][nt] numpy arrays (one per instance) -> flat device field."""
+        if isinstance(fields, np.ndarray):
+            fields = [fields]
+        host = np.zeros(self.field_elems, dtype=np.complex128 if self.precision == "fp64" else np.complex64)
+        for i, (f, inst) in enumerate(zip(fields, self.instances)):
+            n = int(inst["nr"]) * int(inst["nt"])
+            host[self.offsets[i]:self.offsets[i] + n] = np.asarray(f).reshape(-1)
+        return self.torch.from_numpy(host).to(self.device)
+
+    def unpack(self, field) -> list:
+        host = field.detach().to("cpu").numpy()
+        out = []
+        for i, inst in enumerate(self.instances):
+            nr, nt = int(inst["nr"]), int(inst["nt"])
+            out.append(host[self.offsets[i]:self.offsets[i] + nr * nt].reshape(nr, nt).copy())
+        return out
+
+    def _field_ptr(self, field):
+        if field.device != self.device or field.dtype != self.cdtype or not field.is_contiguous():
+            raise FcnError(FCN_E_ARG, "field must be a contiguous device tensor of the plan's dtype")
+        if field.numel() < self.field_elems:
+            raise FcnError(FCN_E_SIZE, "field tensor is smaller than the plan's field")
+        return ctypes.c_void_p(field.data_ptr())
+
+    # ---------------------------------------------------------------- entry points
+    def step(self, field, nsteps: int):
+        self._check(self.lib.fcn_step(self._h, self._field_ptr(field), int(nsteps)))
+
+    def propagate(self, field, nsteps: int, diag_every: int = 0, dz_log=None, replay: bool = False):
+        """Steps and returns (diag tensor [records][diag_record] or None)."""
+        diag = None
+        dptr = None
+        if diag_every > 0:
+            nrec = nsteps // diag_every + 1
+            diag = self.torch.zeros((nrec, self.diag_record), dtype=self.torch.float64, device=self.device)
+            dptr = ctypes.c_void_p(diag.data_ptr())
+        lptr = None
+        if dz_log is not None:
+            if dz_log.dtype != self.torch.float64 or dz_log.numel() < nsteps * self.batch:
+                raise FcnError(FCN_E_ARG, "dz_log must be float64 with nsteps*batch entries")
+            lptr = ctypes.c_void_p(dz_log.data_ptr())
+        self._check(self.lib.fcn_propagate(self._h, self._field_ptr(field), int(nsteps), dptr,
+                                           int(diag_every), lptr, int(replay)))
+        return diag
+
+    def step_timed(self, field, nsteps: int):
+        """Steps with HIP events between passes; returns (row_ms, col_ms, total_ms) means."""
+        r, c, t = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.fcn_step_timed(self._h, self._field_ptr(field), int(nsteps), ctypes.byref(r),
+                                            ctypes.byref(c), ctypes.byref(t)))
+        return r.value, c.value, t.value
+
+    def stage(self, stage: int, field, length: float = 0.0):
+        self._check(self.lib.fcn_stage(self._h, int(stage), self._field_ptr(field), float(length)))
+
+    def diagnostics(self, field):
+        diag = self.torch.zeros(self.diag_record, dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.fcn_diagnostics(self._h, self._field_ptr(field), ctypes.c_void_p(diag.data_ptr())))
+        return diag
+
+    def split_diag(self, record) -> list:
+        """One diagnostics record -> list of per-instance dicts (scalars + fluence array)."""
+        rec = record.detach().to("cpu").numpy() if hasattr(record, "detach") else np.asarray(record)
+        out, off = [], 0
+        for inst in self.instances:
+            nr = int(inst["nr"])
+            d = {k: float(rec[off + j]) for j, k in enumerate(DIAG_NAMES)}
+            d["fluence"] = rec[off + DIAG_SCALARS:off + DIAG_SCALARS + nr].copy()
+            out.append(d)
+            off += DIAG_SCALARS + nr
+        return out
+
+    def sync(self):
+        self._check(self.lib.fcn_sync(self._h))
+
+    def close(self):
+        if self._h:
+            self.lib.fcn_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,118 @@
+"""The C-ABI library loads, exports every entry point include/fcn.h declares, and rejects
+invalid plans on the host (no GPU call is made by these tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1507_05988_amd import fcn, workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "fcn.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:fcn_status|const char \*)\s*(fcn_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fcn.LIB_PATH):
+        from paper_1507_05988_amd import build
+        build.build()
+    return fcn.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(fcn.EXPORTED)
+
+
+def _create(lib, insts, **opt):
+    arr = (fcn.Instance * len(insts))(*[fcn.make_instance(i) for i in insts])
+    o = fcn.Options(precision=opt.get("precision", 0), adaptive=opt.get("adaptive", 0),
+                    max_phase=opt.get("max_phase", 0.05), dz_min=opt.get("dz_min", 1e-6),
+                    dz_max=opt.get("dz_max", 1e-2), use_graph=0, col_tile=opt.get("col_tile", 0),
+                    col_rows=opt.get("col_rows", 0), reserved=0)
+    h = ctypes.c_void_p()
+    rc = lib.fcn_plan_create(arr, len(insts), ctypes.byref(o), ctypes.byref(h))
+    return rc, h
+
+
+def test_plan_sizes_on_host(lib):
+    insts = wl.config_batch(count=5)
+    rc, h = _create(lib, insts, precision=1)
+    assert rc == fcn.FCN_OK
+    sz = ctypes.c_size_t()
+    assert lib.fcn_field_size(h, ctypes.byref(sz)) == 0
+    assert sz.value == sum(i["nr"] * i["nt"] for i in insts)
+    offs = []
+    for i in range(5):
+        assert lib.fcn_field_offset(h, i, ctypes.byref(sz)) == 0
+        offs.append(sz.value)
+    assert offs[0] == 0 and all(offs[i + 1] - offs[i] == insts[i]["nr"] * insts[i]["nt"] for i in range(4))
+    assert lib.fcn_field_offset(h, 5, ctypes.byref(sz)) == fcn.FCN_E_ARG
+    assert lib.fcn_diag_record_size(h, ctypes.byref(sz)) == 0
+    assert sz.value == sum(8 + i["nr"] for i in insts)
+    assert lib.fcn_plan_workspace_size(h, ctypes.byref(sz)) == 0 and sz.value > 0
+    # compute calls before bind are refused with a state error
+    assert lib.fcn_step(h, ctypes.c_void_p(0x1000), 1) == fcn.FCN_E_STATE
+    assert b"not bound" in lib.fcn_last_error(h)
+    assert lib.fcn_plan_destroy(h) == 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nt", 100, fcn.FCN_E_ARG),          # not a power of two
+    ("nt", 16384, fcn.FCN_E_SIZE),       # beyond the largest FFT
+    ("nr", 2, fcn.FCN_E_ARG),
+    ("nr", 4096, fcn.FCN_E_SIZE),
+    ("r_max", -1.0, fcn.FCN_E_ARG),
+    ("t_max", -1.0, fcn.FCN_E_ARG),
+    ("K", 0, fcn.FCN_E_ARG),
+    ("terms", 64, fcn.FCN_E_ARG),
+    ("dz", 0.0, fcn.FCN_E_ARG),          # fixed mode needs dz > 0
+    ("sigma_K", -1.0, fcn.FCN_E_ARG),
+    ("n2", float("nan"), fcn.FCN_E_ARG),
+])
+def test_invalid_instances_rejected(lib, field, value, code):
+    inst = wl.config_small()
+    inst[field] = value
+    rc, h = _create(lib, [inst])
+    assert rc == code
+    assert not h.value
+
+
+def test_invalid_options_rejected(lib):
+    inst = wl.config_small()
+    assert _create(lib, [inst], precision=7)[0] == fcn.FCN_E_ARG
+    assert _create(lib, [inst], adaptive=1, max_phase=0.0)[0] == fcn.FCN_E_ARG
+    assert _create(lib, [inst], adaptive=1, dz_min=1e-2, dz_max=1e-3)[0] == fcn.FCN_E_ARG
+    assert _create(lib, [inst], col_tile=3)[0] == fcn.FCN_E_ARG
+    assert _create(lib, [inst], col_rows=5)[0] == fcn.FCN_E_ARG
+    rc, h = _create(lib, [inst], adaptive=1)
+    assert rc == 0
+    lib.fcn_plan_destroy(h)
+
+
+def test_bind_rejects_bad_workspace(lib):
+    rc, h = _create(lib, [wl.config_small()])
+    assert rc == 0
+    sz = ctypes.c_size_t()
+    lib.fcn_plan_workspace_size(h, ctypes.byref(sz))
+    assert lib.fcn_plan_bind(h, None, sz.value, None) == fcn.FCN_E_ARG
+    assert lib.fcn_plan_bind(h, ctypes.c_void_p(0x1001), sz.value, None) == fcn.FCN_E_ARG  # misaligned
+    assert lib.fcn_plan_bind(h, ctypes.c_void_p(0x1000), sz.value - 1, None) == fcn.FCN_E_SIZE
+    lib.fcn_plan_destroy(h)
+
+
+def test_plan_without_gpu_raises():
+    """The Python Plan has no CPU path: without a GPU it refuses to run."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(fcn.FcnError):
+        fcn.Plan(wl.config_small())

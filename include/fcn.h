@@ -63,7 +63,7 @@ enum { FCN_FP64 = 0, FCN_FP32 = 1 };
 /* One pulse and its grid. */
 typedef struct {
     int32_t nr;              /* radial points, 3 <= nr <= 2048; row nr-1 is r = r_max (A = 0) */
-    int32_t nt;              /* time points, a power of two in [256, 8192] */
+    int32_t nt;              /* time points, a power of two in [64, 8192] */
     double r_max;            /* [m] */
     double t_min, t_max;     /* [s]; periodic window, t_max excluded */
     double lambda0;          /* carrier wavelength [m] */
@@ -86,9 +86,9 @@ typedef struct {
     double max_phase;        /* [rad] per step, adaptive mode */
     double dz_min, dz_max;   /* [m], adaptive mode */
     int32_t use_graph;       /* 1: replay the step body as a captured HIP graph */
-    int32_t col_tile;        /* 0: auto; else frequencies per column workgroup (8, 16 or 32) */
+    int32_t col_tile;        /* 0: auto; else frequencies per column workgroup (4, 8, 16 or 32) */
     int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (8 or 16) */
-    int32_t reserved;
+    int32_t reserved;        /* must be 0 */
 } fcn_options;
 
 /* Number of doubles per instance in one diagnostics record: 8 scalars then nr fluence values.
@@ -161,10 +161,11 @@ const char *fcn_last_error(fcn_plan_t plan);
 /* Releases the host-side plan.  Device buffers stay owned by the caller. */
 fcn_status fcn_plan_destroy(fcn_plan_t plan);
 
-/* fcn_step with a HIP event recorded on the bound stream between every pass of the steady
- * steps; waits for the stream, then returns the mean duration [ms] of the fused row pass
- * (iFFT, two nonlinear half steps, FFT) and of the column pass (CN solve), and the total
- * elapsed time of the call.  For kernel timing; 2 <= nsteps <= 100000. */
+/* fcn_step with HIP events recorded at the start and end of every pass of the steady steps
+ * (by the kernels themselves, so launch gaps are excluded); waits for the stream, then
+ * returns the mean duration [ms] of the fused row pass (iFFT, two nonlinear half steps, FFT)
+ * and of the column pass (CN solve), and the total elapsed time of the call.  For kernel
+ * timing; 2 <= nsteps <= 100000. */
 fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, double *row_ms, double *col_ms,
                           double *total_ms);
 

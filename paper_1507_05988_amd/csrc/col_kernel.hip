@@ -25,6 +25,8 @@
 // No pivoting is needed: with W = diag(1/8, 1, 2, ...) the operator dz/2 L is
 // W-skew-Hermitian, so after the diagonal similarity W^(1/2) the matrix I - dz/2 L has
 // Hermitian part I, which keeps every elimination (any symmetric ordering) well posed.
+#include <hip/hip_ext.h>
+
 #include "fcn_internal.h"
 #include "cplx.hpp"
 
@@ -41,7 +43,13 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     extern __shared__ unsigned char smem_raw[];
     Eq<R> *red = reinterpret_cast<Eq<R> *>(smem_raw);  // [W][2S]
 
-    const ColItem it = a.items[blockIdx.x];
+    // Workgroups are dispatched round-robin over the 8 XCDs (b -> XCD b mod 8).  Give each
+    // XCD a contiguous range of column tiles so tiles sharing 128-byte lines (W*sizeof < 128)
+    // meet in the same L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
+    const int tile = xcd * per + min(xcd, rem) + (b >> 3);
+    const ColItem it = a.items[tile];
     const DevInst in = a.inst[it.inst];
     const int nr = in.nr, nt = in.nt;
     const int t = threadIdx.x;
@@ -224,29 +232,32 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
 }
 
 template <typename R, int W, int L>
-static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s) {
+static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int S = (nr + L - 1) / L;
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
     const size_t shm = sizeof(Eq<R>) * (size_t)W * 2 * S;
-    hipLaunchKernelGGL((col_kernel<R, W, L>), dim3(grid), dim3(threads), shm, s, a);
+    hipExtLaunchKernelGGL((col_kernel<R, W, L>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1, 0, a);
     return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t launch_col_p(int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s) {
-    if (w == 4 && l == 8) return launch_col_t<R, 4, 8>(nr, a, grid, s);
-    if (w == 4 && l == 16) return launch_col_t<R, 4, 16>(nr, a, grid, s);
-    if (w == 8 && l == 8) return launch_col_t<R, 8, 8>(nr, a, grid, s);
-    if (w == 8 && l == 16) return launch_col_t<R, 8, 16>(nr, a, grid, s);
-    if (w == 16 && l == 8) return launch_col_t<R, 16, 8>(nr, a, grid, s);
-    if (w == 16 && l == 16) return launch_col_t<R, 16, 16>(nr, a, grid, s);
-    if (w == 32 && l == 8) return launch_col_t<R, 32, 8>(nr, a, grid, s);
+static hipError_t launch_col_p(int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
+    if (w == 4 && l == 8) return launch_col_t<R, 4, 8>(nr, a, grid, s, e0, e1);
+    if (w == 4 && l == 16) return launch_col_t<R, 4, 16>(nr, a, grid, s, e0, e1);
+    if (w == 8 && l == 8) return launch_col_t<R, 8, 8>(nr, a, grid, s, e0, e1);
+    if (w == 8 && l == 16) return launch_col_t<R, 8, 16>(nr, a, grid, s, e0, e1);
+    if (w == 16 && l == 8) return launch_col_t<R, 16, 8>(nr, a, grid, s, e0, e1);
+    if (w == 16 && l == 16) return launch_col_t<R, 16, 16>(nr, a, grid, s, e0, e1);
+    if (w == 32 && l == 8) return launch_col_t<R, 32, 8>(nr, a, grid, s, e0, e1);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s) {
-    return precision == 0 ? launch_col_p<double>(w, l, nr, a, grid, s) : launch_col_p<float>(w, l, nr, a, grid, s);
+hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s, hipEvent_t e0,
+                      hipEvent_t e1) {
+    return precision == 0 ? launch_col_p<double>(w, l, nr, a, grid, s, e0, e1)
+                          : launch_col_p<float>(w, l, nr, a, grid, s, e0, e1);
 }
 
 }  // namespace fcn

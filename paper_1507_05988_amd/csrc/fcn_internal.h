@@ -37,7 +37,14 @@ struct DevInst {
     double need_rho;        // 1 if the density enters N (plasma or collisional)
     double phi_kerr;        // 1 if the Kerr rate enters Phi
     double phi_plasma;      // k0/(2 rho_c) if the plasma rate enters Phi, else 0
-    double pad0;
+    double need_ik1;        // 1 if I^(K-1) is used (MPA on, or the density scan)
+    // FP32 nonlinear step on the scaled intensity u = I / I_ref, I_ref = (sigma_K dtau)^(-1/K)
+    // when the density is on (so sigma_K I^K dtau = u^K), else 1/|ck1| (or 1):
+    float f_inv_iref;       // 1 / I_ref
+    float fk1, fk2, fk3, fk4;  // ck_j I_ref^j
+    float f_mpa;            // c_mpa I_ref^(K-1)
+    float f_ghalf;          // unused padding
+    float f_pad;
 };
 
 // Mutable device state, one per plan, inside the workspace.
@@ -70,6 +77,8 @@ enum : int {
     RK_FFT_OUT = 16,    // forward FFT, write the spectrum
     RK_STORE = 32,      // write the row back (time domain unless RK_FFT_OUT)
     RK_STAGE_LEN = 64,  // stage test: NL_B uses the explicit length argument as its exponent
+    RK_SCAN = 128,      // some instance of the launch has a density term: contiguous-chunk
+                        // layout and the density scan (otherwise pointwise, strided layout)
 };
 
 // Step-length source of a row kernel.
@@ -113,9 +122,11 @@ struct ColArgs {
 };
 
 // Launchers (defined in the kernel translation units).
+// e0/e1: optional events recorded at the kernel's start and end (nullptr: none).
 hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid,
-                      hipStream_t s);
-hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s);
+                      hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int row_rows_per_group(int nt, int elems);
 hipError_t launch_finalize(const DevInst *inst, int batch, const double *row_diag, const double *zpos,
                            const double *dz_ring, const DevState *state, double *out, hipStream_t s);

@@ -47,15 +47,39 @@ __device__ __forceinline__ constexpr double cos16(int j) {
 }
 __device__ __forceinline__ constexpr double sin16(int j) { return cos16(j - 4); }
 
+// Product of x and a constant C held as C_hi + C_lo (C_hi = C rounded to R, C_lo the
+// rounded remainder): one rounding of the full product.  Rounding C alone to FP32 would
+// shrink or stretch every product by the same relative amount (|W_8|^2 = 1 - 4e-8 with
+// cos(pi/4) rounded), a bias the FFT would apply identically at every z-step.
+template <typename R>
+__device__ __forceinline__ R mul_const(R x, double c) {
+    const R hi = R(c);
+    const R lo = R(c - (double)hi);
+    return fma(x, hi, x * lo);
+}
+template <typename R>
+__device__ __forceinline__ R mul_const2(R x, double cx, R y, double cy) {  // x cx + y cy
+    const R xh = R(cx), xl = R(cx - (double)xh);
+    const R yh = R(cy), yl = R(cy - (double)yh);
+    return fma(x, xh, fma(y, yh, x * xl + y * yl));
+}
+
 // x * W_N^k with W_N = exp(DIR 2 pi i / N), N <= 16, k compile-time after unrolling.
 template <typename R, int N, int DIR>
 __device__ __forceinline__ c2<R> mul_wn(c2<R> x, int k) {
     if (k == 0) return x;
     if (4 * k == N) return mk<R>(-R(DIR) * x.y, R(DIR) * x.x);  // times DIR*i
     const int j = (16 / N) * k;
-    const R c = R(cos16(j));
-    const R s = R(DIR) * R(sin16(j));
-    return mk<R>(x.x * c - x.y * s, x.x * s + x.y * c);
+    const double c = cos16(j);
+    const double s = double(DIR) * sin16(j);
+    if (j == 2 || j == 6 || j == 10 || j == 14) {
+        // |c| = |s| = 1/sqrt(2): s = c gives (c (x - y), c (x + y)); s = -c gives
+        // (c (x + y), c (y - x)); one sum, one difference and two products by c
+        const R u = (c == s) ? x.x - x.y : x.x + x.y;
+        const R v = (c == s) ? x.x + x.y : x.y - x.x;
+        return mk<R>(mul_const<R>(u, c), mul_const<R>(v, c));
+    }
+    return mk<R>(mul_const2<R>(x.x, c, x.y, -s), mul_const2<R>(x.x, s, x.y, c));
 }
 
 // In-register DFT of N = 1, 2, 4, 8 or 16 points, radix-2 decimation in time.
@@ -99,6 +123,8 @@ struct StockhamPass {
     static constexpr bool LAST = (NS * RADIX == NT);
 
     // v holds this pass's inputs: v[q*RADIX + r] = x[j + r*NT/RADIX], j = tr + q*T.
+    // tw: HALF = false: W_NT^k for k < NT; HALF = true: k < NT/2 (W^(k+NT/2) = -W^k).
+    template <bool HALF>
     static __device__ __forceinline__ void run(c2<R> (&v)[E], c2<R> *lds, int tr, const c2<R> *__restrict__ tw) {
 #pragma unroll
         for (int q = 0; q < BF; q++) {
@@ -107,7 +133,14 @@ struct StockhamPass {
                 const int jm = j & (NS - 1);
 #pragma unroll
                 for (int r = 1; r < RADIX; r++) {
-                    const c2<R> w = tw[jm * r * (NT / (NS * RADIX))];
+                    const int idx = jm * r * (NT / (NS * RADIX));
+                    c2<R> w;
+                    if constexpr (HALF) {
+                        w = tw[idx & (NT / 2 - 1)];
+                        if (idx >= NT / 2) w = mk<R>(-w.x, -w.y);
+                    } else {
+                        w = tw[idx];
+                    }
                     v[q * RADIX + r] = (DIR < 0) ? cmul<R>(v[q * RADIX + r], w) : cmulc<R>(v[q * RADIX + r], w);
                 }
             }
@@ -138,17 +171,18 @@ struct StockhamPass {
 #pragma unroll
                 for (int r = 0; r < Next::RADIX; r++)
                     v[q * Next::RADIX + r] = lds[lpad(tr + q * T + r * (NT / Next::RADIX))];
-            Next::run(v, lds, tr, tw);
+            Next::template run<HALF>(v, lds, tr, tw);
         }
     }
 };
 
 // Full transform, strided layout in and out.  DIR = -1 forward, +1 inverse (unscaled).
-// Every thread of the workgroup must call it (it contains barriers).
-template <typename R, int NT, int E, int DIR>
+// HALF: tw holds the first NT/2 table entries only.  Every thread of the workgroup must
+// call it (it contains barriers).
+template <typename R, int NT, int E, int DIR, bool HALF = false>
 __device__ __forceinline__ void row_fft(c2<R> (&v)[E], c2<R> *lds, int tr, const c2<R> *__restrict__ tw) {
     static_assert(NT >= E && (NT & (NT - 1)) == 0, "NT must be a power of two >= E");
-    StockhamPass<R, NT, E, DIR, 1>::run(v, lds, tr, tw);
+    StockhamPass<R, NT, E, DIR, 1>::template run<HALF>(v, lds, tr, tw);
 }
 
 }  // namespace fcn

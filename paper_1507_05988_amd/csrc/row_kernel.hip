@@ -21,36 +21,97 @@
 // A <- A exp(h Re N) (cos(h Im N) + i sin(h Im N)) with N of Eq. nonlinearpart.
 // Intensity, density, N and the diagnostics are FP64 in both precisions; the FP32 path
 // rounds h Re N and h Im N to FP32 before expf/sincosf.
+#include <hip/hip_ext.h>
+
+#include <type_traits>
+
 #include "fcn_internal.h"
 #include "fft.hpp"
 
 namespace fcn {
 
+// x^k for 0 <= k < 32 by square-and-multiply over a fixed five bits (no data-dependent
+// branches; k is uniform across the workgroup).
 __device__ __forceinline__ double ipow(double x, int k) {
     double r = 1.0;
-    while (k > 0) {
-        if (k & 1) r *= x;
+#pragma unroll
+    for (int b = 0; b < 5; b++) {
+        r = (k & (1 << b)) ? r * x : r;
         x *= x;
-        k >>= 1;
+    }
+    return r;
+}
+
+// A exp(decay + i phase) written as A + A delta with
+//   delta = expm1(decay) (cos phase + i sin phase) + (cos phase - 1) + i sin phase,
+//   cos phase - 1 = -2 sin^2(phase/2),  sin phase = 2 sin(phase/2) cos(phase/2),
+// so every small quantity keeps full relative precision.  Rounding exp(decay) and
+// cos(phase) themselves next to 1 would bias |A| by up to half an ulp per update, the
+// same way at every step (a systematic energy drift in FP32).
+__device__ __forceinline__ float ipowf_(float x, int k) {
+    float r = 1.0f;
+#pragma unroll
+    for (int b = 0; b < 5; b++) {
+        r = (k & (1 << b)) ? r * x : r;
+        x *= x;
     }
     return r;
 }
 
 template <typename R>
 __device__ __forceinline__ c2<R> nl_rotate(c2<R> a, double decay, double phase);
+// sin and cos of |x| <= 0.4 by their Taylor series through x^9 and x^10 (truncation below
+// 1e-12 relative), expm1 of |x| <= 0.1 through x^7 (below 3e-12); other arguments take
+// the library functions.  Nonlinear phases per half step are usually in this range.
+__device__ __forceinline__ void sincos_small(float x, float *s, float *c) {
+    if (fabsf(x) <= 0.4f) {
+        const float x2 = x * x;
+        *s = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f + x2 * (-1.0f / 5040.0f + x2 * (1.0f / 362880.0f)))));
+        *c = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f + x2 * (-1.0f / 720.0f + x2 * (1.0f / 40320.0f +
+                                                                                  x2 * (-1.0f / 3628800.0f)))));
+    } else {
+        sincosf(x, s, c);
+    }
+}
+__device__ __forceinline__ float expm1_small(float x) {
+    if (fabsf(x) <= 0.1f)
+        return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f +
+                                                                                   x * (1.0f / 720.0f +
+                                                                                        x * (1.0f / 5040.0f)))))));
+    return expm1f(x);
+}
+
+__device__ __forceinline__ c2<float> nl_rotate_f(c2<float> a, float decay, float phase) {
+    const float em1 = expm1_small(decay);
+    float sh, ch;
+    sincos_small(0.5f * phase, &sh, &ch);
+    const float sn = 2.0f * sh * ch;
+    const float c1 = -2.0f * sh * sh;
+    const float dr = em1 * (1.0f + c1) + c1;
+    const float di = sn * (1.0f + em1);
+    return mk<float>(a.x + (a.x * dr - a.y * di), a.y + (a.x * di + a.y * dr));
+}
 template <>
 __device__ __forceinline__ c2<float> nl_rotate<float>(c2<float> a, double decay, double phase) {
-    const float e = expf((float)decay);
-    float s, c;
-    sincosf((float)phase, &s, &c);
-    return cmul<float>(a, mk<float>(e * c, e * s));
+    const float em1 = expm1f((float)decay);
+    float sh, ch;
+    sincosf(0.5f * (float)phase, &sh, &ch);
+    const float sn = 2.0f * sh * ch;
+    const float c1 = -2.0f * sh * sh;
+    const float dr = em1 * (1.0f + c1) + c1;
+    const float di = sn * (1.0f + em1);
+    return mk<float>(a.x + (a.x * dr - a.y * di), a.y + (a.x * di + a.y * dr));
 }
 template <>
 __device__ __forceinline__ c2<double> nl_rotate<double>(c2<double> a, double decay, double phase) {
-    const double e = exp(decay);
-    double s, c;
-    sincos(phase, &s, &c);
-    return cmul<double>(a, mk<double>(e * c, e * s));
+    const double em1 = expm1(decay);
+    double sh, ch;
+    sincos(0.5 * phase, &sh, &ch);
+    const double sn = 2.0 * sh * ch;
+    const double c1 = -2.0 * sh * sh;
+    const double dr = em1 * (1.0 + c1) + c1;
+    const double di = sn * (1.0 + em1);
+    return mk<double>(a.x + (a.x * dr - a.y * di), a.y + (a.x * di + a.y * dr));
 }
 
 struct DiagAcc {
@@ -147,50 +208,119 @@ __device__ __forceinline__ DiagAcc row_reduce(DiagAcc v, int tr, RowScratch &sh)
     return v;
 }
 
-// One nonlinear sub-step on the E contiguous points c[] (positions tr*E + k) of a row.
-// i_next: intensity of the point after the chunk (pre-update; unused by the last thread).
-// h: exponent length (dz/2).  APPLY: update c; DIAG: accumulate diagnostics into acc.
-// scan: workgroup-uniform switch for the density scan (it holds barriers when T > 64);
-// rows whose instance has no density term run it with S = 0, which keeps rho = 0.
+// Per-point pieces of the nonlinear operator N (Eq. nonlinearpart) in the kernel's
+// arithmetic.  FP64 kernels evaluate everything in FP64.  FP32 kernels work on the scaled
+// intensity u = I / I_ref (see DevInst): the Kerr rate, the multiphoton term and the RK4
+// quantities dtau sigma_K I^K = u^K (exactly, with I_ref = (sigma_K dtau)^(-1/K)) are FP32 and
+// cannot overflow; the density itself is always accumulated in FP64.
+template <typename R>
+struct NlPoint;
+
+template <>
+struct NlPoint<double> {
+    double I, ik1;  // I and I^(K-1)
+    __device__ __forceinline__ void load(c2<double> a, const DevInst &in, bool k1) {
+        I = a.x * a.x + a.y * a.y;
+        ik1 = k1 ? ipow(I, in.K - 1) : 0.0;
+    }
+    __device__ __forceinline__ double intensity() const { return I; }
+    __device__ __forceinline__ double dt_g(const DevInst &in) const { return in.dtau * in.sigma_K * ik1 * I; }
+    static __device__ __forceinline__ double dt_g_of(double Imid, const DevInst &in) {
+        return in.dtau * in.sigma_K * ipow(Imid, in.K);
+    }
+    __device__ __forceinline__ double mid_arg(const NlPoint &o) const { return 0.5 * (I + o.I); }
+    __device__ __forceinline__ double kerr(const DevInst &in) const {
+        return I * (in.ck1 + I * (in.ck2 + I * (in.ck3 + I * in.ck4)));
+    }
+    __device__ __forceinline__ c2<double> apply(c2<double> a, const DevInst &in, double h, double rho) const {
+        const double im_n = kerr(in) + in.c_plasma * rho;
+        const double re_n = in.c_mpa * ik1 + in.c_coll * rho;
+        return nl_rotate<double>(a, h * re_n, h * im_n);
+    }
+};
+
+template <>
+struct NlPoint<float> {
+    float ii, u, uk1;  // I, I/I_ref, (I/I_ref)^(K-1)
+    __device__ __forceinline__ void load(c2<float> a, const DevInst &in, bool k1) {
+        ii = a.x * a.x + a.y * a.y;
+        u = ii * in.f_inv_iref;
+        uk1 = k1 ? ipowf_(u, in.K - 1) : 0.0f;
+    }
+    __device__ __forceinline__ double intensity() const { return (double)ii; }
+    __device__ __forceinline__ float dt_g(const DevInst &) const { return uk1 * u; }
+    static __device__ __forceinline__ float dt_g_of(float umid, const DevInst &in) { return ipowf_(umid, in.K); }
+    __device__ __forceinline__ float mid_arg(const NlPoint &o) const { return 0.5f * (u + o.u); }
+    __device__ __forceinline__ double kerr(const DevInst &in) const {
+        return (double)(u * (in.fk1 + u * (in.fk2 + u * (in.fk3 + u * in.fk4))));
+    }
+    __device__ __forceinline__ c2<float> apply(c2<float> a, const DevInst &in, float h, double rho,
+                                               bool with_rho) const {
+        const float kr = u * (in.fk1 + u * (in.fk2 + u * (in.fk3 + u * in.fk4)));
+        if (!with_rho) return nl_rotate_f(a, h * (in.f_mpa * uk1), h * kr);
+        const double im_n = (double)kr + in.c_plasma * rho;
+        const double re_n = (double)(in.f_mpa * uk1) + in.c_coll * rho;
+        return nl_rotate_f(a, (float)((double)h * re_n), (float)((double)h * im_n));
+    }
+    __device__ __forceinline__ c2<float> apply(c2<float> a, const DevInst &in, float h, double rho) const {
+        return apply(a, in, h, rho, true);
+    }
+};
+
+// One nonlinear sub-step A <- A exp(h N) on the E points c[] of a thread.
+//  scan = true: c[] holds the contiguous points tr*E + k of the row and nx the point after
+//    the chunk (pre-update; for the last thread any value, it only feeds the unused last
+//    interval).  The density follows from the RK4 affine maps scanned over the row.  With
+//    upd_next, nx is also advanced with the density reached at the end of the chunk, so the
+//    next sub-step has its neighbour intensity without another LDS exchange.
+//  scan = false (no density term in the workgroup): pointwise, any layout, nx unused.
+// Must be called by every thread of the workgroup (the scan holds barriers when T > 64).
 template <typename R, int T, int E>
-__device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], const DevInst &in, double i_next, double h, bool apply,
-                                            bool diag, bool scan, DiagAcc &acc, int tr, RowScratch &sh) {
-    double inten[E];
+__device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevInst &in, R h, bool apply,
+                                            bool diag, bool scan, bool upd_next, DiagAcc &acc, int tr,
+                                            RowScratch &sh) {
+    using S_t = decltype(NlPoint<R>{}.dt_g(in));
+    const bool k1 = in.need_ik1 != 0.0;
+    NlPoint<R> pt[E];
 #pragma unroll
-    for (int k = 0; k < E; k++) inten[k] = (double)c[k].x * (double)c[k].x + (double)c[k].y * (double)c[k].y;
+    for (int k = 0; k < E; k++) pt[k].load(c[k], in, k1);
 
     double rho[E];
-    const bool need_rho = in.need_rho != 0.0;
+    double rho_end = 0.0;
+    NlPoint<R> pn;
     if (scan) {
-        const double dt = in.dtau, sk = in.sigma_K, ra = in.rho_at;
-        const int K = in.K;
-        double S[E];
+        pn.load(nx, in, k1);
+        const bool need_rho = in.need_rho != 0.0;
+        const double ra = in.rho_at;
+        S_t S[E];
         double ca = 1.0, cb = 0.0;
-        double g0 = sk * ipow(inten[0], K);
+        S_t a0 = pt[0].dt_g(in);
 #pragma unroll
         for (int k = 0; k < E; k++) {
-            const double i1 = (k + 1 < E) ? inten[k + 1] : i_next;
-            const double g1 = sk * ipow(i1, K);
-            const double gh = sk * ipow(0.5 * (inten[k] + i1), K);
-            // classical RK4 step of d rho/dt = g(t)(rho_at - rho) over dt:
+            const NlPoint<R> &p1 = (k + 1 < E) ? pt[k + 1] : pn;
+            const S_t a1 = p1.dt_g(in);
+            const S_t ah = NlPoint<R>::dt_g_of(pt[k].mid_arg(p1), in);
+            // one classical RK4 step of d rho/dt = g(t) (rho_at - rho), in units of dt g:
             // rho' = rho + S (rho_at - rho)
-            const double a0 = dt * g0, ah = dt * gh, a1 = dt * g1;
-            const double u2 = 1.0 - 0.5 * a0;
-            const double u3 = 1.0 - 0.5 * ah * u2;
-            const double u4 = 1.0 - ah * u3;
-            const double s = (a0 + 2.0 * ah * u2 + 2.0 * ah * u3 + a1 * u4) * (1.0 / 6.0);
-            S[k] = need_rho ? s : 0.0;
-            // compose this step after the chunk's earlier steps
-            cb = (1.0 - S[k]) * cb + S[k] * ra;
-            ca = (1.0 - S[k]) * ca;
-            g0 = g1;
+            const S_t one = S_t(1), half = S_t(0.5);
+            const S_t u2 = one - half * a0;
+            const S_t u3 = one - half * ah * u2;
+            const S_t u4 = one - ah * u3;
+            const S_t sv = (a0 + S_t(2) * ah * u2 + S_t(2) * ah * u3 + a1 * u4) * S_t(1.0 / 6.0);
+            S[k] = need_rho ? sv : S_t(0);
+            const double sd = (double)S[k];
+            cb = (1.0 - sd) * cb + sd * ra;  // compose after the chunk's earlier steps
+            ca = (1.0 - sd) * ca;
+            a0 = a1;
         }
         double r = row_exclusive_scan<T>(ca, cb, tr, sh);
 #pragma unroll
         for (int k = 0; k < E; k++) {
             rho[k] = r;
-            r = (1.0 - S[k]) * r + S[k] * ra;
+            const double sd = (double)S[k];
+            r = (1.0 - sd) * r + sd * ra;
         }
+        rho_end = r;
     } else {
 #pragma unroll
         for (int k = 0; k < E; k++) rho[k] = 0.0;
@@ -198,20 +328,21 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], const DevInst &in, do
 
 #pragma unroll
     for (int k = 0; k < E; k++) {
-        const double I = inten[k];
-        const double kerr = I * (in.ck1 + I * (in.ck2 + I * (in.ck3 + I * in.ck4)));
-        const double im_n = kerr + in.c_plasma * rho[k];
         if (diag) {
+            const double I = pt[k].intensity();
             acc.sum += I;
             acc.imax = fmax(acc.imax, I);
             acc.rmax = fmax(acc.rmax, rho[k]);
-            acc.phimax = fmax(acc.phimax, in.phi_kerr * fabs(kerr) + in.phi_plasma * rho[k]);
+            acc.phimax = fmax(acc.phimax, in.phi_kerr * fabs(pt[k].kerr(in)) + in.phi_plasma * rho[k]);
         }
         if (apply) {
-            const double re_n = in.c_mpa * ipow(I, in.K - 1) + in.c_coll * rho[k];
-            c[k] = nl_rotate<R>(c[k], h * re_n, h * im_n);
+            if constexpr (std::is_same<R, float>::value)
+                c[k] = pt[k].apply(c[k], in, h, rho[k], scan);
+            else
+                c[k] = pt[k].apply(c[k], in, h, rho[k]);
         }
     }
+    if (apply && scan && upd_next) nx = pn.apply(nx, in, h, rho_end);
 }
 
 __device__ __forceinline__ double dz_rule(double phi, double max_phase, double dz_min, double dz_max) {
@@ -229,6 +360,10 @@ struct RowCfg {
     static constexpr int RPW = T >= 256 ? 1 : 256 / T;
     static constexpr int THREADS = T * RPW;
     static constexpr int LROW = NT + NT / 32;
+    // FP32: the first half of the twiddle table is staged in LDS (FP64 kernels keep the
+    // global table: the extra LDS and addressing push them into register spills)
+    static constexpr bool TW_LDS = sizeof(c2<R>) == 8 && sizeof(c2<R>) * (size_t)(RPW * LROW + NT / 2) <= 150 * 1024;
+    static constexpr int TWN = TW_LDS ? NT / 2 : 1;
 };
 
 template <typename R, int NT, int E, int FLAGS>
@@ -239,7 +374,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     constexpr bool BOOK = (FLAGS & RK_STAGE_LEN) == 0 && (FLAGS & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
     constexpr bool NEED_CHUNK = (FLAGS & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
     __shared__ c2<R> lds[RPW * Cfg::LROW];
+    __shared__ c2<R> twl[Cfg::TWN];
     __shared__ RowScratch sh;
+    constexpr bool FFTS = (FLAGS & (RK_IFFT_IN | RK_FFT_OUT)) != 0;
 
     const int tid = threadIdx.x;
     const int tr = tid % T;
@@ -274,40 +411,54 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 #pragma unroll
     for (int k = 0; k < E; k++) v[k] = active ? g[tr + k * T] : czero<R>();
 
+    const c2<R> *twp = tw;
+    if constexpr (FFTS && Cfg::TW_LDS) {
+        for (int i = tid; i < NT / 2; i += Cfg::THREADS) twl[i] = tw[i];
+        __syncthreads();
+        twp = twl;
+    }
+
     if constexpr ((FLAGS & RK_IFFT_IN) != 0) {
-        row_fft<R, NT, E, +1>(v, row_lds, tr, tw);
+        row_fft<R, NT, E, +1, Cfg::TW_LDS>(v, row_lds, tr, twp);
         const R sc = R(1.0 / NT);
 #pragma unroll
         for (int k = 0; k < E; k++) v[k] = cscale<R>(v[k], sc);
     }
 
     if constexpr (NEED_CHUNK) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < E; k++) row_lds[lpad(tr + k * T)] = v[k];
-        __syncthreads();
-        c2<R> c[E];
-#pragma unroll
-        for (int k = 0; k < E; k++) c[k] = row_lds[lpad(tr * E + k)];
         DiagAcc acc{0.0, 0.0, 0.0, 0.0};
-        const bool scan = __syncthreads_or(active && in.need_rho != 0.0) != 0;
-
-        if constexpr ((FLAGS & RK_NL_A) != 0) {
-            c2<R> nx = row_lds[lpad(tr < T - 1 ? tr * E + E : 0)];
-            const double i_next = (double)nx.x * (double)nx.x + (double)nx.y * (double)nx.y;
-            nl_sub_step<R, T, E>(c, in, i_next, 0.5 * dz_a, true, false, scan, acc, tr, sh);
+        // the density scan needs contiguous points per thread; a launch without any density
+        // term applies the nonlinear step pointwise on the strided registers instead
+        constexpr bool scan = (FLAGS & RK_SCAN) != 0;
+        const R ha = R(0.5 * dz_a), hb = R(0.5 * dz_b);
+        constexpr bool DO_A = (FLAGS & RK_NL_A) != 0;
+        constexpr bool DO_B = (FLAGS & RK_NL_B) != 0;
+        constexpr bool DO_D = (FLAGS & RK_DIAG) != 0;
+        if constexpr (scan) {
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < E; k++) row_lds[lpad(tr * E + k)] = c[k];
+            for (int k = 0; k < E; k++) row_lds[lpad(tr + k * T)] = v[k];
             __syncthreads();
-        }
-        if constexpr ((FLAGS & (RK_NL_B | RK_DIAG)) != 0) {
+            c2<R> c[E];
+#pragma unroll
+            for (int k = 0; k < E; k++) c[k] = row_lds[lpad(tr * E + k)];
             c2<R> nx = row_lds[lpad(tr < T - 1 ? tr * E + E : 0)];
-            const double i_next = (double)nx.x * (double)nx.x + (double)nx.y * (double)nx.y;
-            nl_sub_step<R, T, E>(c, in, i_next, 0.5 * dz_b, (FLAGS & RK_NL_B) != 0, (FLAGS & RK_DIAG) != 0, scan, acc,
-                                 tr, sh);
+            if constexpr (DO_A) nl_sub_step<R, T, E>(c, nx, in, ha, true, false, true, true, acc, tr, sh);
+            if constexpr (DO_B || DO_D) nl_sub_step<R, T, E>(c, nx, in, hb, DO_B, DO_D, true, false, acc, tr, sh);
+            if constexpr ((FLAGS & RK_STORE) != 0) {
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < E; k++) row_lds[lpad(tr * E + k)] = c[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < E; k++) v[k] = row_lds[lpad(tr + k * T)];
+            }
+        } else {
+            c2<R> unused = czero<R>();
+            if constexpr (DO_A) nl_sub_step<R, T, E>(v, unused, in, ha, true, false, false, false, acc, tr, sh);
+            if constexpr (DO_B || DO_D) nl_sub_step<R, T, E>(v, unused, in, hb, DO_B, DO_D, false, false, acc, tr, sh);
         }
-        if constexpr ((FLAGS & RK_DIAG) != 0) {
+        if constexpr (DO_D) {
             acc = row_reduce<T>(acc, tr, sh);
             if (active && tr == 0) {
                 double *rd = a.row_diag + 4 * (int64_t)(in.row_base + it.m);
@@ -325,17 +476,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
                 }
             }
         }
-        if constexpr ((FLAGS & RK_STORE) != 0) {
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < E; k++) row_lds[lpad(tr * E + k)] = c[k];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < E; k++) v[k] = row_lds[lpad(tr + k * T)];
-        }
     }
 
-    if constexpr ((FLAGS & RK_FFT_OUT) != 0) row_fft<R, NT, E, -1>(v, row_lds, tr, tw);
+    if constexpr ((FLAGS & RK_FFT_OUT) != 0) row_fft<R, NT, E, -1, Cfg::TW_LDS>(v, row_lds, tr, twp);
 
     if constexpr ((FLAGS & RK_STORE) != 0) {
         if (active) {
@@ -359,25 +502,27 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 
 // ------------------------------------------------------------------ launch table
 
+// Launches go through hipExtLaunchKernelGGL: with non-null events it records them at the
+// kernel's own start and end (timing without the gaps between launches).
 template <typename R, int NT, int FLAGS>
-static hipError_t launch_row_t(const RowArgs &a, int grid, hipStream_t s) {
+static hipError_t launch_row_t(const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     constexpr int E = 8;
     using Cfg = RowCfg<R, NT, E, FLAGS>;
-    hipLaunchKernelGGL((row_kernel<R, NT, E, FLAGS>), dim3(grid), dim3(Cfg::THREADS), 0, s, a);
+    hipExtLaunchKernelGGL((row_kernel<R, NT, E, FLAGS>), dim3(grid), dim3(Cfg::THREADS), 0, s, e0, e1, 0, a);
     return hipGetLastError();
 }
 
 template <typename R, int FLAGS>
-static hipError_t launch_row_nt(int nt, const RowArgs &a, int grid, hipStream_t s) {
+static hipError_t launch_row_nt(int nt, const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (nt) {
-        case 64: return launch_row_t<R, 64, FLAGS>(a, grid, s);
-        case 128: return launch_row_t<R, 128, FLAGS>(a, grid, s);
-        case 256: return launch_row_t<R, 256, FLAGS>(a, grid, s);
-        case 512: return launch_row_t<R, 512, FLAGS>(a, grid, s);
-        case 1024: return launch_row_t<R, 1024, FLAGS>(a, grid, s);
-        case 2048: return launch_row_t<R, 2048, FLAGS>(a, grid, s);
-        case 4096: return launch_row_t<R, 4096, FLAGS>(a, grid, s);
-        case 8192: return launch_row_t<R, 8192, FLAGS>(a, grid, s);
+        case 64: return launch_row_t<R, 64, FLAGS>(a, grid, s, e0, e1);
+        case 128: return launch_row_t<R, 128, FLAGS>(a, grid, s, e0, e1);
+        case 256: return launch_row_t<R, 256, FLAGS>(a, grid, s, e0, e1);
+        case 512: return launch_row_t<R, 512, FLAGS>(a, grid, s, e0, e1);
+        case 1024: return launch_row_t<R, 1024, FLAGS>(a, grid, s, e0, e1);
+        case 2048: return launch_row_t<R, 2048, FLAGS>(a, grid, s, e0, e1);
+        case 4096: return launch_row_t<R, 4096, FLAGS>(a, grid, s, e0, e1);
+        case 8192: return launch_row_t<R, 8192, FLAGS>(a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -392,15 +537,21 @@ constexpr int RK_T_IFFT = RK_IFFT_IN | RK_STORE;
 constexpr int RK_T_NL = RK_NL_B | RK_STORE | RK_STAGE_LEN;
 
 template <typename R>
-static hipError_t launch_row_p(int nt, int flags, const RowArgs &a, int grid, hipStream_t s) {
+static hipError_t launch_row_p(int nt, int flags, const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
     switch (flags) {
-        case RK_FIRST: return launch_row_nt<R, RK_FIRST>(nt, a, grid, s);
-        case RK_MIDDLE: return launch_row_nt<R, RK_MIDDLE>(nt, a, grid, s);
-        case RK_LAST: return launch_row_nt<R, RK_LAST>(nt, a, grid, s);
-        case RK_DIAG_ONLY: return launch_row_nt<R, RK_DIAG_ONLY>(nt, a, grid, s);
-        case RK_T_FFT: return launch_row_nt<R, RK_T_FFT>(nt, a, grid, s);
-        case RK_T_IFFT: return launch_row_nt<R, RK_T_IFFT>(nt, a, grid, s);
-        case RK_T_NL: return launch_row_nt<R, RK_T_NL>(nt, a, grid, s);
+        case RK_FIRST: return launch_row_nt<R, RK_FIRST>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE: return launch_row_nt<R, RK_MIDDLE>(nt, a, grid, s, e0, e1);
+        case RK_LAST: return launch_row_nt<R, RK_LAST>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY: return launch_row_nt<R, RK_DIAG_ONLY>(nt, a, grid, s, e0, e1);
+        case RK_T_NL: return launch_row_nt<R, RK_T_NL>(nt, a, grid, s, e0, e1);
+        case RK_FIRST | RK_SCAN: return launch_row_nt<R, RK_FIRST | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE | RK_SCAN: return launch_row_nt<R, RK_MIDDLE | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_LAST | RK_SCAN: return launch_row_nt<R, RK_LAST | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY | RK_SCAN: return launch_row_nt<R, RK_DIAG_ONLY | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_T_NL | RK_SCAN: return launch_row_nt<R, RK_T_NL | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_T_FFT: return launch_row_nt<R, RK_T_FFT>(nt, a, grid, s, e0, e1);
+        case RK_T_IFFT: return launch_row_nt<R, RK_T_IFFT>(nt, a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -410,9 +561,11 @@ int row_rows_per_group(int nt, int elems) {
     return t >= 256 ? 1 : 256 / t;
 }
 
-hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid, hipStream_t s) {
+hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid, hipStream_t s,
+                      hipEvent_t e0, hipEvent_t e1) {
     if (elems != 8) return hipErrorInvalidValue;
-    return precision == 0 ? launch_row_p<double>(nt, flags, a, grid, s) : launch_row_p<float>(nt, flags, a, grid, s);
+    return precision == 0 ? launch_row_p<double>(nt, flags, a, grid, s, e0, e1)
+                          : launch_row_p<float>(nt, flags, a, grid, s, e0, e1);
 }
 
 // ------------------------------------------------------------------ small kernels

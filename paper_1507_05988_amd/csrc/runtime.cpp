@@ -41,6 +41,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct RowBucket {
     int nt;
+    int scan;  // RK_SCAN when an instance of the bucket has a density term
     int item_off, nitems;
     int grid;
 };
@@ -168,6 +169,36 @@ void twiddle_table(int nt, std::vector<double> &re, std::vector<double> &im) {
     }
 }
 
+// FP32 twiddle from FP64 (c, s): among the float pairs within one ulp of each component,
+// the one whose modulus is closest to 1 (ties: closest to the FP64 value).  Plain
+// rounding leaves |w|^2 - 1 ~ 1e-7 at fixed entries, which makes the forward/inverse
+// transform pair scale some components the same way at every step.
+void round_unit_f32(double c, double s, float out[2]) {
+    const float c0 = (float)c, s0 = (float)s;
+    float best_c = c0, best_s = s0;
+    double best_m = 1e300, best_d = 1e300;
+    for (int i = -1; i <= 1; i++) {
+        float cc = c0;
+        if (i < 0) cc = std::nextafter(c0, -2.0f);
+        if (i > 0) cc = std::nextafter(c0, 2.0f);
+        for (int j = -1; j <= 1; j++) {
+            float ss = s0;
+            if (j < 0) ss = std::nextafter(s0, -2.0f);
+            if (j > 0) ss = std::nextafter(s0, 2.0f);
+            const double m = std::fabs((double)cc * cc + (double)ss * ss - 1.0);
+            const double d = std::fabs((double)cc - c) + std::fabs((double)ss - s);
+            if (m < best_m || (m == best_m && d < best_d)) {
+                best_m = m;
+                best_d = d;
+                best_c = cc;
+                best_s = ss;
+            }
+        }
+    }
+    out[0] = best_c;
+    out[1] = best_s;
+}
+
 bool col_tiles_supported(int w, int l) {
     return (w == 4 && (l == 8 || l == 16)) || (w == 8 && (l == 8 || l == 16)) || (w == 16 && (l == 8 || l == 16)) ||
            (w == 32 && l == 8);
@@ -176,7 +207,7 @@ bool col_tiles_supported(int w, int l) {
 // Column tile choice: frequencies per workgroup W and rows per thread L.
 void choose_col_tiles(int precision, int nr, const fcn_options &opt, int &w, int &l) {
     l = opt.col_rows ? opt.col_rows : (precision == 0 ? 8 : 16);
-    w = opt.col_tile ? opt.col_tile : (precision == 0 ? 8 : 16);
+    w = opt.col_tile ? opt.col_tile : 4;
     // keep the workgroup within 512 threads
     while (w * ((nr + l - 1) / l) > 512 && w > 4) w /= 2;
     while (w * ((nr + l - 1) / l) > 512 && l < 16) l *= 2;
@@ -205,7 +236,8 @@ fcn_status build_plan(fcn_plan_t p) {
                 double v[2] = {re[k], im[k]};
                 memcpy(&p->twiddles[e * 16], v, 16);
             } else {
-                float v[2] = {(float)re[k], (float)im[k]};
+                float v[2];
+                round_unit_f32(re[k], im[k], v);
                 memcpy(&p->twiddles[e * 8], v, 8);
             }
         }
@@ -265,6 +297,20 @@ fcn_status build_plan(fcn_plan_t p) {
         d.need_rho = ((in.terms & (FCN_PLASMA | FCN_COLL)) != 0 && in.rho_at > 0.0 && in.sigma_K > 0.0) ? 1.0 : 0.0;
         d.phi_kerr = kerr ? 1.0 : 0.0;
         d.phi_plasma = (in.terms & FCN_PLASMA) ? k0 / (2.0 * rho_c) : 0.0;
+        d.need_ik1 = (d.need_rho != 0.0 || d.c_mpa != 0.0) ? 1.0 : 0.0;
+        double iref = 1.0;
+        if (d.need_rho != 0.0)
+            iref = std::pow(in.sigma_K * d.dtau, -1.0 / (double)in.K);
+        else if (d.ck1 != 0.0)
+            iref = 1.0 / std::fabs(d.ck1);
+        else if (d.c_mpa != 0.0)
+            iref = std::pow(std::fabs(d.c_mpa), -1.0 / (double)std::max(in.K - 1, 1));
+        d.f_inv_iref = (float)(1.0 / iref);
+        d.fk1 = (float)(d.ck1 * iref);
+        d.fk2 = (float)(d.ck2 * iref * iref);
+        d.fk3 = (float)(d.ck3 * iref * iref * iref);
+        d.fk4 = (float)(d.ck4 * iref * iref * iref * iref);
+        d.f_mpa = (float)(d.c_mpa * std::pow(iref, (double)(in.K - 1)));
         p->dinst[i] = d;
         off += (size_t)in.nr * in.nt;
         row += in.nr;
@@ -284,6 +330,9 @@ fcn_status build_plan(fcn_plan_t p) {
         for (int i : kv.second)
             for (int m = 0; m < p->insts[i].nr; m++) p->row_items.push_back(RowItem{i, m});
         b.nitems = (int)p->row_items.size() - b.item_off;
+        b.scan = 0;
+        for (int i : kv.second)
+            if (p->dinst[i].need_rho != 0.0) b.scan = RK_SCAN;
         const int rpw = row_rows_per_group(b.nt, kRowElems);
         b.grid = (b.nitems + rpw - 1) / rpw;
         p->row_buckets.push_back(b);
@@ -381,26 +430,37 @@ struct StepCtx {
     int replay = 0;
 };
 
-hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, int seed, double stage_len = 0.0) {
-    for (const auto &b : p->row_buckets) {
+// e0 / e1: optional events recorded at the start of the pass's first kernel and the end of
+// its last kernel.
+hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, int seed, double stage_len = 0.0,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    const size_t nb = p->row_buckets.size();
+    for (size_t bi = 0; bi < nb; bi++) {
+        const auto &b = p->row_buckets[bi];
         RowArgs a = row_args(p, field, b);
         a.dz_log = ctx.dz_log;
         a.log_base = ctx.log_base;
         if (ctx.replay && !p->opt.adaptive) a.dz_mode = DZ_REPLAY;
         a.seed_slots = seed;
         a.stage_len = stage_len;
-        hipError_t e = launch_row(p->precision, b.nt, kRowElems, flags, a, b.grid, p->stream);
+        const bool nl = (flags & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
+        hipError_t e = launch_row(p->precision, b.nt, kRowElems, nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
+                                  bi == 0 ? e0 : nullptr, bi + 1 == nb ? e1 : nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0) {
-    for (const auto &b : p->col_buckets) {
+hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0, hipEvent_t e0 = nullptr,
+                    hipEvent_t e1 = nullptr) {
+    const size_t nb = p->col_buckets.size();
+    for (size_t bi = 0; bi < nb; bi++) {
+        const auto &b = p->col_buckets[bi];
         ColArgs a = col_args(p, field, b);
         a.use_stage_len = stage;
         a.stage_len = stage_len;
-        hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, p->stream);
+        hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, p->stream, bi == 0 ? e0 : nullptr,
+                                  bi + 1 == nb ? e1 : nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -544,6 +604,10 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
         return FCN_E_ARG;
     }
     if (p->opt.col_rows && p->opt.col_rows != 8 && p->opt.col_rows != 16) {
+        delete p;
+        return FCN_E_ARG;
+    }
+    if (p->opt.reserved != 0) {
         delete p;
         return FCN_E_ARG;
     }
@@ -693,11 +757,10 @@ fcn_status fcn_step_timed(fcn_plan_t p, void *field_dev, int64_t nsteps, double 
     if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
     if (!field_dev || !row_ms || !col_ms || !total_ms) return fail(p, FCN_E_ARG, "NULL argument");
     if (nsteps < 2 || nsteps > 100000) return fail(p, FCN_E_ARG, "nsteps must be in [2, 100000]");
-    // Steady steps s = 0 .. mid-1 each run a column pass then a fused row pass.
-    // ev[0]: start; ev[1]: after the first row pass; ev[2s+2]: after column pass s;
-    // ev[2s+3]: after row pass s; ev[2 mid + 2]: after the closing passes.
+    // Steady steps s = 0 .. mid-1 each run a column pass then a fused row pass; each pass is
+    // bracketed by events recorded at its kernels' own start and end.
     const int64_t mid = nsteps - 1;
-    std::vector<hipEvent_t> ev((size_t)(2 * mid + 3), nullptr);
+    std::vector<hipEvent_t> ev((size_t)(4 * mid + 2), nullptr);
     hipError_t e = hipSuccess;
     for (auto &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
@@ -706,29 +769,25 @@ fcn_status fcn_step_timed(fcn_plan_t p, void *field_dev, int64_t nsteps, double 
         e = row_pass(p, field_dev, F_DIAG, ctx, 1);
         p->seeded = true;
     }
-    if (e == hipSuccess) e = hipEventRecord(ev[0], p->stream);
-    if (e == hipSuccess) e = row_pass(p, field_dev, F_FIRST, ctx, 0);
-    if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
+    hipEvent_t t0 = ev[4 * mid], t1 = ev[4 * mid + 1];
+    if (e == hipSuccess) e = row_pass(p, field_dev, F_FIRST, ctx, 0, 0.0, t0, nullptr);
     for (int64_t s = 0; s < mid && e == hipSuccess; s++) {
-        e = col_pass(p, field_dev, 0);
-        if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 2], p->stream);
-        if (e == hipSuccess) e = row_pass(p, field_dev, F_MIDDLE, ctx, 0);
-        if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 3], p->stream);
+        e = col_pass(p, field_dev, 0, 0.0, ev[4 * s], ev[4 * s + 1]);
+        if (e == hipSuccess) e = row_pass(p, field_dev, F_MIDDLE, ctx, 0, 0.0, ev[4 * s + 2], ev[4 * s + 3]);
     }
     if (e == hipSuccess) e = col_pass(p, field_dev, 0);
-    if (e == hipSuccess) e = row_pass(p, field_dev, F_LAST, ctx, 0);
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * mid + 2], p->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * mid + 2]);
+    if (e == hipSuccess) e = row_pass(p, field_dev, F_LAST, ctx, 0, 0.0, nullptr, t1);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
     double rsum = 0.0, csum = 0.0;
     float tot = 0.f;
     for (int64_t s = 0; s < mid && e == hipSuccess; s++) {
         float c = 0.f, r = 0.f;
-        e = hipEventElapsedTime(&c, ev[2 * s + 1], ev[2 * s + 2]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&r, ev[2 * s + 2], ev[2 * s + 3]);
+        e = hipEventElapsedTime(&c, ev[4 * s], ev[4 * s + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&r, ev[4 * s + 2], ev[4 * s + 3]);
         csum += c;
         rsum += r;
     }
-    if (e == hipSuccess) e = hipEventElapsedTime(&tot, ev[0], ev[2 * mid + 2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&tot, t0, t1);
     for (auto &x : ev)
         if (x) hipEventDestroy(x);
     if (e != hipSuccess) return hip_fail(p, e, "timed step");

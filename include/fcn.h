@@ -173,6 +173,76 @@ fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, doub
  * column solve, elements per thread of the row kernel. */
 fcn_status fcn_plan_tiles(fcn_plan_t plan, int32_t *col_tile, int32_t *col_rows, int32_t *row_elems);
 
+/* ------------------------------------------------------------------------------------
+ * Learned coarse z-propagator (an addition of this project, not in the paper): a complex
+ * convolutional operator on the (r, t) grid, 4 valid 5x5 complex convolutions
+ * 1 -> C -> C -> C -> 1 complex channels with complex biases and CReLU (ReLU of the real and
+ * the imaginary part) after layers 1-3.  A window of H x W output points reads an 8-point
+ * halo of the field.  Used as G(U) = C(U) + s Net(U/s), C one classical FCN step of the
+ * window length, as the coarse solver of parareal (with s = in_scale^-1 and an output
+ * scale out_scale = kappa s per sample, the network predicts (F - C) / (kappa s)).  Parameters: caller-owned FP32 buffer
+ * of fcn_net_param_count floats, per layer W[co][ci][5][5] as (re, im) pairs then b[co] as
+ * (re, im); gradients have the same layout and are the pairs (dL/dRe w, dL/dIm w).
+ * Activations are stored in BF16 (act_bf16 = 1) or FP32 and accumulated in FP32.
+ * All network calls are asynchronous on the bound stream except fcn_net_loss. */
+typedef struct fcn_net_s *fcn_net_t;
+
+/* One network sample: a window of one instance's complex FP32 field (element offsets into
+ * the flat field buffers).  Device arrays of this struct are read by the kernels. */
+typedef struct {
+    int64_t field_off;   /* input window (fcn_net_input, fcn_net_target: fine field) or the
+                            destination (fcn_net_apply) */
+    int64_t coarse_off;  /* coarse field C(U) (fcn_net_target, fcn_net_apply) */
+    int32_t row0, col0;  /* first r row and t column of the window */
+    float in_scale;      /* the network input is the field times in_scale */
+    float out_scale;     /* the network output is (fine - coarse) / out_scale */
+} fcn_net_sample;
+
+fcn_status fcn_net_create(int32_t channels, int32_t act_bf16, fcn_net_t *out);
+fcn_status fcn_net_param_count(fcn_net_t net, size_t *nfloats);
+/* Workspace for up to max_batch windows of max_h x max_w outputs; training = 1 keeps every
+ * activation and the gradient buffers. */
+fcn_status fcn_net_workspace_size(fcn_net_t net, int32_t max_batch, int32_t max_h, int32_t max_w,
+                                  int32_t training, size_t *bytes);
+/* Binds caller-owned device buffers (params; for training also grads, Adam m and v, each
+ * fcn_net_param_count floats) and a 256-byte aligned workspace; expands the weights. */
+fcn_status fcn_net_bind(fcn_net_t net, float *params, float *grads, float *adam_m, float *adam_v, void *workspace,
+                        size_t workspace_bytes, int32_t max_batch, int32_t max_h, int32_t max_w, int32_t training,
+                        void *stream);
+/* Re-expands the weights after the caller changed params. */
+fcn_status fcn_net_refresh(fcn_net_t net);
+/* Network input of `batch` windows (device array `samples`) from complex FP32 fields [nr][nt]:
+ * rows row0-8 .. row0+h+7 (row -m reads row m: A is even in r; rows >= nr read 0) and
+ * columns col0-8 .. col0+w+7 (periodic in t), times in_scale. */
+fcn_status fcn_net_input(fcn_net_t net, const void *fields, const fcn_net_sample *samples, int32_t batch,
+                         int32_t nr, int32_t nt, int32_t h, int32_t w);
+/* Forward pass of the current input; out (optional) receives FP32 [batch][2][h][w]. */
+fcn_status fcn_net_forward(fcn_net_t net, int32_t batch, int32_t h, int32_t w, float *out);
+/* Training target (fine - coarse) / out_scale on the windows, FP32 [batch][2][h][w]. */
+fcn_status fcn_net_target(fcn_net_t net, const void *fine, const void *coarse, const fcn_net_sample *samples,
+                          int32_t batch, int32_t nr, int32_t nt, int32_t h, int32_t w, float *target);
+/* Loss of the last forward output: mean over the batch of sum_r w_r |out - target|^2 /
+ * sum_r w_r |target|^2, w_r = global r index (1/8 on the axis), rows row0_host[b] + y.
+ * Synchronous (waits for the stream); with_grad also stores dloss/dout for fcn_net_backward. */
+fcn_status fcn_net_loss(fcn_net_t net, const float *target, const int32_t *row0_host, int32_t batch, int32_t h,
+                        int32_t w, int32_t with_grad, double *loss);
+/* Parameter gradients of the loss (overwrites grads). */
+fcn_status fcn_net_backward(fcn_net_t net, int32_t batch, int32_t h, int32_t w);
+/* One Adam update of params from grads (bias-corrected), then re-expansion. */
+fcn_status fcn_net_adam(fcn_net_t net, float lr, float beta1, float beta2, float eps);
+/* dst = coarse + out_scale * (last full-grid forward output) for each sample's whole field
+ * (h = nr, w = nt in the preceding forward); the r_max row is kept 0. */
+fcn_status fcn_net_apply(fcn_net_t net, const void *coarse, const fcn_net_sample *samples, int32_t batch, int32_t nr,
+                         int32_t nt, void *dst);
+const char *fcn_net_last_error(fcn_net_t net);
+fcn_status fcn_net_destroy(fcn_net_t net);
+
+/* Parareal correction of one window (complex FP32 fields [nr][nt]):
+ * u_new = g_new + f_old - g_old, and FP64 partial sums of the r-weighted |u_new - u_prev|^2
+ * and |u_new|^2 in part_dev[2k], part_dev[2k+1] for k < nparts (nparts workgroups). */
+fcn_status fcn_parareal_update(const void *g_new, const void *f_old, const void *g_old, const void *u_prev,
+                               void *u_new, int32_t nr, int32_t nt, double *part_dev, int32_t nparts, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

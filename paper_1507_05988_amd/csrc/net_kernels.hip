@@ -1,0 +1,479 @@
+// net_kernels.hip -- kernels of the learned coarse z-propagator: a complex-valued
+// convolutional operator on the (r, t) grid (4 layers of 5x5 complex convolutions,
+// 1 -> C -> C -> C -> 1 complex channels, CReLU between layers), its gradients and its
+// optimiser, plus the helpers that cut network inputs and targets out of FCN fields and
+// apply the network's correction.  Not part of the paper (an addition of this project).
+//
+// A complex layer with weights W = Wr + i Wi acts on (re, im) channel pairs as the real
+// layer [[Wr, -Wi], [Wi, Wr]]: the kernels below are real 5x5 convolutions on 2C real
+// channels, and the complex parameters are expanded to / contracted from that form.
+// Activations are stored as FP32 or BF16 (type A), every sum is accumulated in FP32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "net_internal.h"
+
+namespace fcn {
+
+// ---------------------------------------------------------------- activation storage
+
+__device__ __forceinline__ float ld_act(const float *p, size_t i) { return p[i]; }
+__device__ __forceinline__ float ld_act(const bf16_t *p, size_t i) {
+    return __uint_as_float(((uint32_t)p[i].v) << 16);
+}
+__device__ __forceinline__ void st_act(float *p, size_t i, float x) { p[i] = x; }
+// FP32 -> BF16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ void st_act(bf16_t *p, size_t i, float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+        p[i].v = (uint16_t)((u >> 16) | 0x40u);
+        return;
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    p[i].v = (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------- 5x5 convolution
+
+constexpr int CV_TH = 8, CV_TW = 32, CV_CIT = 8, CV_COT = 16;
+
+// out[b][co][y][x] = bias[co] + sum_{ci,ky,kx} in[b][ci][y+ky-pad][x+kx-pad] w[co][ci][ky][kx]
+// (in read as 0 outside [0,Hin) x [0,Win)), ReLU when relu != 0.  Valid convolution with
+// pad = 0; with pad = 4, flipped and transposed weights it is the input gradient.
+// Grid: x = ceil(Wout/32), y = ceil(Hout/8), z = B * ceil(Cout/16); 256 threads.
+template <typename AI, typename AO>
+__global__ void __launch_bounds__(256) conv5_kernel(const AI *__restrict__ in, const float *__restrict__ w,
+                                                    const float *__restrict__ bias, AO *__restrict__ out, int Cin,
+                                                    int Hin, int Win, int Cout, int Hout, int Wout, int pad,
+                                                    int relu) {
+    __shared__ float s_in[CV_CIT][CV_TH + 4][CV_TW + 5];
+    __shared__ float s_w[CV_COT][CV_CIT][25];
+    const int co_groups = (Cout + CV_COT - 1) / CV_COT;
+    const int b = blockIdx.z / co_groups;
+    const int co0 = (blockIdx.z % co_groups) * CV_COT;
+    const int y0 = blockIdx.y * CV_TH, x0 = blockIdx.x * CV_TW;
+    const int tid = threadIdx.x, ty = tid / CV_TW, tx = tid % CV_TW;
+    float acc[CV_COT];
+#pragma unroll
+    for (int c = 0; c < CV_COT; c++) acc[c] = 0.0f;
+
+    for (int ci0 = 0; ci0 < Cin; ci0 += CV_CIT) {
+        constexpr int TILE = (CV_TH + 4) * (CV_TW + 4);
+        for (int idx = tid; idx < CV_CIT * TILE; idx += 256) {
+            const int ci = idx / TILE, rem = idx % TILE;
+            const int yy = rem / (CV_TW + 4), xx = rem % (CV_TW + 4);
+            const int gy = y0 + yy - pad, gx = x0 + xx - pad;
+            float v = 0.0f;
+            if (ci0 + ci < Cin && gy >= 0 && gy < Hin && gx >= 0 && gx < Win)
+                v = ld_act(in, (((size_t)b * Cin + ci0 + ci) * Hin + gy) * Win + gx);
+            s_in[ci][yy][xx] = v;
+        }
+        for (int idx = tid; idx < CV_COT * CV_CIT * 25; idx += 256) {
+            const int c = idx / (CV_CIT * 25), rem = idx % (CV_CIT * 25);
+            const int ci = rem / 25, k = rem % 25;
+            float v = 0.0f;
+            if (co0 + c < Cout && ci0 + ci < Cin) v = w[((size_t)(co0 + c) * Cin + ci0 + ci) * 25 + k];
+            s_w[c][ci][k] = v;
+        }
+        __syncthreads();
+        const int nci = min(CV_CIT, Cin - ci0);
+        for (int ci = 0; ci < nci; ci++) {
+#pragma unroll
+            for (int ky = 0; ky < 5; ky++)
+#pragma unroll
+                for (int kx = 0; kx < 5; kx++) {
+                    const float v = s_in[ci][ty + ky][tx + kx];
+#pragma unroll
+                    for (int c = 0; c < CV_COT; c++) acc[c] = fmaf(v, s_w[c][ci][ky * 5 + kx], acc[c]);
+                }
+        }
+        __syncthreads();
+    }
+    const int y = y0 + ty, x = x0 + tx;
+    if (y < Hout && x < Wout) {
+#pragma unroll
+        for (int c = 0; c < CV_COT; c++) {
+            const int co = co0 + c;
+            if (co < Cout) {
+                float v = acc[c] + (bias ? bias[co] : 0.0f);
+                if (relu) v = fmaxf(v, 0.0f);
+                st_act(out, (((size_t)b * Cout + co) * Hout + y) * Wout + x, v);
+            }
+        }
+    }
+}
+
+// gw[co][ci][ky][kx] = sum_{b,y<Hout,x<Wout} in[b][ci][y+ky][x+kx] g[b][co][y][x]
+// gb[co] = sum g[b][co][y][x] (written by the ci = 0 block).  One workgroup per (co, ci)
+// and a fixed reduction tree: deterministic.
+template <typename AI>
+__global__ void __launch_bounds__(256) conv5_wgrad_kernel(const AI *__restrict__ in, const float *__restrict__ g,
+                                                          float *__restrict__ gw, float *__restrict__ gb, int B,
+                                                          int Cin, int Hin, int Win, int Cout, int Hout, int Wout) {
+    const int co = blockIdx.x / Cin, ci = blockIdx.x % Cin;
+    float acc[26];
+#pragma unroll
+    for (int k = 0; k < 26; k++) acc[k] = 0.0f;
+    const size_t npx = (size_t)B * Hout * Wout;
+    for (size_t p = threadIdx.x; p < npx; p += 256) {
+        const int x = (int)(p % Wout);
+        const int y = (int)((p / Wout) % Hout);
+        const int b = (int)(p / ((size_t)Wout * Hout));
+        const float gv = g[(((size_t)b * Cout + co) * Hout + y) * Wout + x];
+        const size_t base = (((size_t)b * Cin + ci) * Hin + y) * Win + x;
+#pragma unroll
+        for (int ky = 0; ky < 5; ky++)
+#pragma unroll
+            for (int kx = 0; kx < 5; kx++) acc[ky * 5 + kx] = fmaf(ld_act(in, base + (size_t)ky * Win + kx), gv, acc[ky * 5 + kx]);
+        acc[25] += gv;
+    }
+    __shared__ float red[256][27];
+#pragma unroll
+    for (int k = 0; k < 26; k++) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int k = 0; k < 26; k++) red[threadIdx.x][k] += red[threadIdx.x + h][k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 25) gw[((size_t)co * Cin + ci) * 25 + threadIdx.x] = red[0][threadIdx.x];
+    if (threadIdx.x == 25 && ci == 0 && gb) gb[co] = red[0][25];
+}
+
+// g[i] *= (act[i] > 0): gradient through ReLU, from the stored post-activation.
+template <typename A>
+__global__ void relu_mask_kernel(float *g, const A *act, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(ld_act(act, i) > 0.0f)) g[i] = 0.0f;
+}
+
+// ---------------------------------------------------------------- complex <-> real weights
+
+// Complex layer parameters: W[co][ci][25] as (re, im) pairs, then b[co] as (re, im).
+// Real form: Wr[2co+a][2ci+c][25] with blocks [[re, -im], [im, re]], br[2co+a].
+__global__ void expand_weights_kernel(const float *pc, float *wr, float *br, int cout, int cin) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = cout * cin * 25;
+    if (i < nw) {
+        const int k = i % 25, ci = (i / 25) % cin, co = i / (25 * cin);
+        const float re = pc[2 * i], im = pc[2 * i + 1];
+        const int C2 = 2 * cin;
+        wr[((size_t)(2 * co) * C2 + 2 * ci) * 25 + k] = re;
+        wr[((size_t)(2 * co) * C2 + 2 * ci + 1) * 25 + k] = -im;
+        wr[((size_t)(2 * co + 1) * C2 + 2 * ci) * 25 + k] = im;
+        wr[((size_t)(2 * co + 1) * C2 + 2 * ci + 1) * 25 + k] = re;
+    } else if (i < nw + cout) {
+        const int co = i - nw;
+        br[2 * co] = pc[2 * nw + 2 * co];
+        br[2 * co + 1] = pc[2 * nw + 2 * co + 1];
+    }
+}
+
+// wT[ci][co][24-k] = w[co][ci][k]: weights of the input-gradient convolution.
+__global__ void flip_transpose_kernel(const float *w, float *wt, int cout, int cin) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cout * cin * 25) return;
+    const int k = i % 25, ci = (i / 25) % cin, co = i / (25 * cin);
+    wt[((size_t)ci * cout + co) * 25 + (24 - k)] = w[i];
+}
+
+// Wirtinger-pair gradient of the complex parameters from the real-form gradients:
+// dL/dRe W = G[2co][2ci] + G[2co+1][2ci+1],  dL/dIm W = -G[2co][2ci+1] + G[2co+1][2ci].
+__global__ void contract_grads_kernel(const float *gwr, const float *gbr, float *gc, int cout, int cin) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = cout * cin * 25;
+    const int C2 = 2 * cin;
+    if (i < nw) {
+        const int k = i % 25, ci = (i / 25) % cin, co = i / (25 * cin);
+        const float g00 = gwr[((size_t)(2 * co) * C2 + 2 * ci) * 25 + k];
+        const float g01 = gwr[((size_t)(2 * co) * C2 + 2 * ci + 1) * 25 + k];
+        const float g10 = gwr[((size_t)(2 * co + 1) * C2 + 2 * ci) * 25 + k];
+        const float g11 = gwr[((size_t)(2 * co + 1) * C2 + 2 * ci + 1) * 25 + k];
+        gc[2 * i] = g00 + g11;
+        gc[2 * i + 1] = g10 - g01;
+    } else if (i < nw + cout) {
+        const int co = i - nw;
+        gc[2 * nw + 2 * co] = gbr[2 * co];
+        gc[2 * nw + 2 * co + 1] = gbr[2 * co + 1];
+    }
+}
+
+// ---------------------------------------------------------------- optimiser and loss
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, size_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// r weight of crop row y: the global radial index row0 + y (1/8 on the axis row).
+__device__ __forceinline__ double rweight(int m) { return m == 0 ? 0.125 : (double)m; }
+
+// Per sample b: num = sum w (pred - tgt)^2, den = sum w tgt^2 over 2 x H x W (FP64), one
+// workgroup per sample, fixed tree.  out[2b] = num, out[2b+1] = den.
+__global__ void __launch_bounds__(256) loss_reduce_kernel(const float *pred, const float *tgt, const int *row0, int H,
+                                                          int W, double *out) {
+    const int b = blockIdx.x;
+    const size_t n = (size_t)2 * H * W;
+    double num = 0.0, den = 0.0;
+    for (size_t i = threadIdx.x; i < n; i += 256) {
+        const int y = (int)((i / W) % H);
+        const double w = rweight(row0[b] + y);
+        const double p = pred[b * n + i], t = tgt[b * n + i];
+        num += w * (p - t) * (p - t);
+        den += w * t * t;
+    }
+    __shared__ double sn[256], sd[256];
+    sn[threadIdx.x] = num;
+    sd[threadIdx.x] = den;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sn[threadIdx.x] += sn[threadIdx.x + h];
+            sd[threadIdx.x] += sd[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * b] = sn[0];
+        out[2 * b + 1] = sd[0];
+    }
+}
+
+// loss = (1/B) sum_b num_b / den_b; grad = dloss/dpred = 2 w (pred - tgt) / (B den_b)
+__global__ void loss_grad_kernel(const float *pred, const float *tgt, const int *row0, int B, int H, int W,
+                                 const double *nd, float *grad) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n = (size_t)2 * H * W;
+    if (i >= n * B) return;
+    const int b = (int)(i / n);
+    const int y = (int)((i % n) / W) % H;
+    const double den = nd[2 * b + 1] > 0.0 ? nd[2 * b + 1] : 1.0;
+    grad[i] = (float)(2.0 * rweight(row0[b] + y) * ((double)pred[i] - (double)tgt[i]) / ((double)B * den));
+}
+
+// ---------------------------------------------------------------- fields <-> network tensors
+
+// Network input for sample b: rows row0-8 .. row0+H+7 and columns col0-8 .. col0+W+7 of the
+// complex field of its instance, scaled by in_scale: row -m reads row m (the field is even in
+// r, dA/dr = 0 at the axis), rows >= nr read 0 (A = 0 at r_max), columns wrap (periodic t).
+// out[b][0|1][H+16][W+16] (re, im planes).
+template <typename A>
+__global__ void net_input_kernel(const float2 *fields, const NetSample *smp, int nr, int nt, int H, int W, A *out) {
+    const int Hp = H + 16, Wp = W + 16;
+    const size_t per = (size_t)Hp * Wp;
+    const int b = blockIdx.y;
+    const NetSample s = smp[b];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+        const int yy = (int)(i / Wp), xx = (int)(i % Wp);
+        int r = s.row0 - 8 + yy;
+        if (r < 0) r = -r;
+        int t = (s.col0 - 8 + xx) % nt;
+        if (t < 0) t += nt;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (r < nr) v = fields[s.field_off + (size_t)r * nt + t];
+        st_act(out, ((size_t)b * 2 + 0) * per + i, v.x * s.in_scale);
+        st_act(out, ((size_t)b * 2 + 1) * per + i, v.y * s.in_scale);
+    }
+}
+
+// Training target for sample b: (fine - coarse) / out_scale on rows row0.., columns col0..,
+// out[b][0|1][H][W].
+__global__ void net_target_kernel(const float2 *fine, const float2 *coarse, const NetSample *smp, int nr, int nt,
+                                  int H, int W, float *out) {
+    const size_t per = (size_t)H * W;
+    const int b = blockIdx.y;
+    const NetSample s = smp[b];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / W), x = (int)(i % W);
+        const int r = s.row0 + y;
+        int t = (s.col0 + x) % nt;
+        if (t < 0) t += nt;
+        float2 d = make_float2(0.0f, 0.0f);
+        if (r >= 0 && r < nr) {
+            const float2 f = fine[s.field_off + (size_t)r * nt + t];
+            const float2 c = coarse[s.coarse_off + (size_t)r * nt + t];
+            d = make_float2(f.x - c.x, f.y - c.y);
+        }
+        const float rs = 1.0f / s.out_scale;
+        out[((size_t)b * 2 + 0) * per + i] = d.x * rs;
+        out[((size_t)b * 2 + 1) * per + i] = d.y * rs;
+    }
+}
+
+// Full-grid correction: dst[r][t] = base[r][t] + out_scale * (net re + i net im); the r_max row
+// stays 0.  net[b][0|1][nr][nt] with sample b the whole grid of its instance.
+__global__ void net_apply_kernel(const float *net, const float2 *base, const NetSample *smp, int nr, int nt,
+                                 float2 *dst) {
+    const size_t per = (size_t)nr * nt;
+    const int b = blockIdx.y;
+    const NetSample s = smp[b];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i / nt);
+        const float2 c = base[s.coarse_off + i];
+        const float sc = s.out_scale;
+        float2 o = make_float2(c.x + sc * net[((size_t)b * 2 + 0) * per + i], c.y + sc * net[((size_t)b * 2 + 1) * per + i]);
+        if (r == nr - 1) o = make_float2(0.0f, 0.0f);
+        dst[s.field_off + i] = o;
+    }
+}
+
+// Parareal correction U_new = G_new + F_old - G_old on one window field (complex FP32), with
+// per-workgroup FP64 partial sums of |U_new - U_prev|^2 and |U_new|^2 (r-weighted):
+// part[2 * blockIdx.x] and part[2 * blockIdx.x + 1].
+__global__ void __launch_bounds__(256) parareal_update_kernel(const float2 *g_new, const float2 *f_old,
+                                                              const float2 *g_old, const float2 *u_prev,
+                                                              float2 *u_new, int nr, int nt, double *part) {
+    const size_t n = (size_t)nr * nt;
+    double dn = 0.0, un = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float2 a = g_new[i], f = f_old[i], g = g_old[i];
+        const float2 u = make_float2(a.x + (f.x - g.x), a.y + (f.y - g.y));
+        const float2 q = u_prev[i];
+        const double w = rweight((int)(i / nt));
+        dn += w * ((double)(u.x - q.x) * (u.x - q.x) + (double)(u.y - q.y) * (u.y - q.y));
+        un += w * ((double)u.x * u.x + (double)u.y * u.y);
+        u_new[i] = u;
+    }
+    __shared__ double s1[256], s2[256];
+    s1[threadIdx.x] = dn;
+    s2[threadIdx.x] = un;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+            s2[threadIdx.x] += s2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename AI, typename AO>
+static hipError_t conv5_t(const AI *in, const float *w, const float *bias, AO *out, int B, int Cin, int Hin, int Win,
+                          int Cout, int Hout, int Wout, int pad, int relu, hipStream_t s) {
+    const int cg = (Cout + CV_COT - 1) / CV_COT;
+    dim3 grid((Wout + CV_TW - 1) / CV_TW, (Hout + CV_TH - 1) / CV_TH, B * cg);
+    hipLaunchKernelGGL((conv5_kernel<AI, AO>), grid, dim3(256), 0, s, in, w, bias, out, Cin, Hin, Win, Cout, Hout,
+                       Wout, pad, relu);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv5(int act_bf16, int in_kind, int out_kind, const void *in, const float *w, const float *bias,
+                        void *out, int B, int Cin, int Hin, int Win, int Cout, int Hout, int Wout, int pad, int relu,
+                        hipStream_t s) {
+    // kinds: 0 = FP32 tensor, 1 = tensor in the network's activation type
+    if (act_bf16) {
+        if (in_kind && out_kind)
+            return conv5_t((const bf16_t *)in, w, bias, (bf16_t *)out, B, Cin, Hin, Win, Cout, Hout, Wout, pad, relu, s);
+        if (in_kind && !out_kind)
+            return conv5_t((const bf16_t *)in, w, bias, (float *)out, B, Cin, Hin, Win, Cout, Hout, Wout, pad, relu, s);
+        if (!in_kind && out_kind)
+            return conv5_t((const float *)in, w, bias, (bf16_t *)out, B, Cin, Hin, Win, Cout, Hout, Wout, pad, relu, s);
+    }
+    return conv5_t((const float *)in, w, bias, (float *)out, B, Cin, Hin, Win, Cout, Hout, Wout, pad, relu, s);
+}
+
+hipError_t launch_conv5_wgrad(int act_bf16, const void *in, const float *g, float *gw, float *gb, int B, int Cin,
+                              int Hin, int Win, int Cout, int Hout, int Wout, hipStream_t s) {
+    if (act_bf16)
+        hipLaunchKernelGGL(conv5_wgrad_kernel<bf16_t>, dim3(Cout * Cin), dim3(256), 0, s, (const bf16_t *)in, g, gw,
+                           gb, B, Cin, Hin, Win, Cout, Hout, Wout);
+    else
+        hipLaunchKernelGGL(conv5_wgrad_kernel<float>, dim3(Cout * Cin), dim3(256), 0, s, (const float *)in, g, gw, gb,
+                           B, Cin, Hin, Win, Cout, Hout, Wout);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(int act_bf16, float *g, const void *act, size_t n, hipStream_t s) {
+    const int grid = (int)((n + 255) / 256);
+    if (act_bf16)
+        hipLaunchKernelGGL(relu_mask_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, g, (const bf16_t *)act, n);
+    else
+        hipLaunchKernelGGL(relu_mask_kernel<float>, dim3(grid), dim3(256), 0, s, g, (const float *)act, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_weights(const float *pc, float *wr, float *br, int cout, int cin, hipStream_t s) {
+    const int n = cout * cin * 25 + cout;
+    hipLaunchKernelGGL(expand_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pc, wr, br, cout, cin);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_transpose(const float *w, float *wt, int cout, int cin, hipStream_t s) {
+    const int n = cout * cin * 25;
+    hipLaunchKernelGGL(flip_transpose_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, wt, cout, cin);
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_grads(const float *gwr, const float *gbr, float *gc, int cout, int cin, hipStream_t s) {
+    const int n = cout * cin * 25 + cout;
+    hipLaunchKernelGGL(contract_grads_kernel, dim3((n + 255) / 256), dim3(256), 0, s, gwr, gbr, gc, cout, cin);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const float *pred, const float *tgt, const int *row0, int B, int H, int W, double *nd,
+                       float *grad, hipStream_t s) {
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(B), dim3(256), 0, s, pred, tgt, row0, H, W, nd);
+    const size_t n = (size_t)B * 2 * H * W;
+    if (grad)
+        hipLaunchKernelGGL(loss_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pred, tgt, row0, B, H,
+                           W, (const double *)nd, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_input(int act_bf16, const float2 *fields, const NetSample *smp, int B, int nr, int nt, int H,
+                            int W, void *out, hipStream_t s) {
+    const size_t per = (size_t)(H + 16) * (W + 16);
+    dim3 grid((unsigned)std::min<size_t>((per + 255) / 256, 4096), B);
+    if (act_bf16)
+        hipLaunchKernelGGL(net_input_kernel<bf16_t>, grid, dim3(256), 0, s, fields, smp, nr, nt, H, W, (bf16_t *)out);
+    else
+        hipLaunchKernelGGL(net_input_kernel<float>, grid, dim3(256), 0, s, fields, smp, nr, nt, H, W, (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_target(const float2 *fine, const float2 *coarse, const NetSample *smp, int B, int nr, int nt,
+                             int H, int W, float *out, hipStream_t s) {
+    const size_t per = (size_t)H * W;
+    dim3 grid((unsigned)std::min<size_t>((per + 255) / 256, 4096), B);
+    hipLaunchKernelGGL(net_target_kernel, grid, dim3(256), 0, s, fine, coarse, smp, nr, nt, H, W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_apply(const float *net, const float2 *base, const NetSample *smp, int B, int nr, int nt,
+                            float2 *dst, hipStream_t s) {
+    const size_t per = (size_t)nr * nt;
+    dim3 grid((unsigned)std::min<size_t>((per + 255) / 256, 4096), B);
+    hipLaunchKernelGGL(net_apply_kernel, grid, dim3(256), 0, s, net, base, smp, nr, nt, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_parareal_update(const float2 *g_new, const float2 *f_old, const float2 *g_old, const float2 *u_prev,
+                                  float2 *u_new, int nr, int nt, double *part, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(parareal_update_kernel, dim3(nblocks), dim3(256), 0, s, g_new, f_old, g_old, u_prev, u_new, nr,
+                       nt, part);
+    return hipGetLastError();
+}
+
+}  // namespace fcn

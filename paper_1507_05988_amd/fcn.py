@@ -25,6 +25,9 @@ EXPORTED = (
     "fcn_plan_create", "fcn_plan_workspace_size", "fcn_field_size", "fcn_field_offset",
     "fcn_diag_record_size", "fcn_plan_bind", "fcn_step", "fcn_propagate", "fcn_diagnostics",
     "fcn_stage", "fcn_sync", "fcn_last_error", "fcn_plan_destroy", "fcn_plan_tiles", "fcn_step_timed",
+    "fcn_net_create", "fcn_net_param_count", "fcn_net_workspace_size", "fcn_net_bind", "fcn_net_refresh",
+    "fcn_net_input", "fcn_net_forward", "fcn_net_target", "fcn_net_loss", "fcn_net_backward", "fcn_net_adam",
+    "fcn_net_apply", "fcn_net_last_error", "fcn_net_destroy", "fcn_parareal_update",
 )
 
 
@@ -45,6 +48,11 @@ class Instance(ctypes.Structure):
         ("dz", ctypes.c_double),
         ("terms", ctypes.c_uint32),
     ]
+
+
+class NetSample(ctypes.Structure):
+    _fields_ = [("field_off", ctypes.c_int64), ("coarse_off", ctypes.c_int64), ("row0", ctypes.c_int32),
+                ("col0", ctypes.c_int32), ("in_scale", ctypes.c_float), ("out_scale", ctypes.c_float)]
 
 
 class Options(ctypes.Structure):
@@ -86,6 +94,21 @@ def load_library(path: str = LIB_PATH):
         "fcn_plan_tiles": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
         "fcn_step_timed": ([vp, vp, i64, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
                            ctypes.c_int),
+        "fcn_net_create": ([i32, i32, plan_p], ctypes.c_int),
+        "fcn_net_param_count": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcn_net_workspace_size": ([vp, i32, i32, i32, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcn_net_bind": ([vp, vp, vp, vp, vp, vp, sz, i32, i32, i32, i32, vp], ctypes.c_int),
+        "fcn_net_refresh": ([vp], ctypes.c_int),
+        "fcn_net_input": ([vp, vp, vp, i32, i32, i32, i32, i32], ctypes.c_int),
+        "fcn_net_forward": ([vp, i32, i32, i32, vp], ctypes.c_int),
+        "fcn_net_target": ([vp, vp, vp, vp, i32, i32, i32, i32, i32, vp], ctypes.c_int),
+        "fcn_net_loss": ([vp, vp, ctypes.POINTER(i32), i32, i32, i32, i32, ctypes.POINTER(dbl)], ctypes.c_int),
+        "fcn_net_backward": ([vp, i32, i32, i32], ctypes.c_int),
+        "fcn_net_adam": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float], ctypes.c_int),
+        "fcn_net_apply": ([vp, vp, vp, i32, i32, i32, vp], ctypes.c_int),
+        "fcn_net_last_error": ([vp], ctypes.c_char_p),
+        "fcn_net_destroy": ([vp], ctypes.c_int),
+        "fcn_parareal_update": ([vp, vp, vp, vp, vp, i32, i32, vp, i32, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

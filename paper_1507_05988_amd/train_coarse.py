@@ -1,0 +1,120 @@
+"""Train the learned coarse z-propagator on FCN trajectories and evaluate it on held-out ones.
+
+Usage: python -m paper_1507_05988_amd.train_coarse [--trajectories 2000] [--channels 32]
+           [--out paper_1507_05988_amd/weights/coarse_c32_bf16.npz] [--time-budget SECONDS]
+
+Trajectory j (seeded, see workloads.config_parareal_trajectory) is generated on the GPU by the
+fine FCN solver; training uses j < 2000 and evaluation the held-out 2000 <= j < 2016.  The
+output scale kappa is the r-weighted RMS of (F - C)/s over the windows of the first group, so
+that the network predicts values of order one.  The saved .npz holds plain arrays only.
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import coarse, fcn
+from . import workloads as wl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "weights", "coarse_c32_bf16.npz")
+HELD_OUT = range(2000, 2016)
+
+
+def estimate_kappa(ids, steps_per_window=wl.PARAREAL_STEPS_PER_WINDOW, windows=wl.PARAREAL_WINDOWS):
+    """r-weighted RMS over the windows of trajectories `ids` of |F(U) - C(U)| / |U| (relative)."""
+    import torch
+
+    insts = [wl.config_parareal_trajectory(j) for j in ids]
+    nr, nt = int(insts[0]["nr"]), int(insts[0]["nt"])
+    fine = fcn.Plan(insts, precision="fp32")
+    crs = fcn.Plan([dict(i, dz=i["dz"] * steps_per_window) for i in insts], precision="fp32")
+    u = fine.pack([wl.gaussian_field(i, np.complex64) for i in insts])
+    c = torch.empty_like(u)
+    vals = []
+    for _ in range(windows):
+        c.copy_(u)
+        crs.step(c, 1)
+        fine.step(u, steps_per_window)
+        for k in range(len(insts)):
+            o = fine.offsets[k]
+            vals.append(coarse._werr(c[o:o + nr * nt], u[o:o + nr * nt], nr, nt))
+    return float(np.sqrt(np.mean(np.square(vals))))
+
+
+def coarse_errors(ids, params=None, channels=32, bf16=True, kappa=1.0,
+                  steps_per_window=wl.PARAREAL_STEPS_PER_WINDOW, windows=wl.PARAREAL_WINDOWS):
+    """Per trajectory and window: r-weighted relative error of G(U_j) against F(U_j), U_j on
+    the fine trajectory.  Returns an array [len(ids)][windows]."""
+    import torch
+
+    out = np.zeros((len(ids), windows))
+    for a, j in enumerate(ids):
+        inst = wl.config_parareal_trajectory(j)
+        nr, nt = int(inst["nr"]), int(inst["nt"])
+        G = coarse.CoarseOperator(inst, steps_per_window, net_params=params, channels=channels, bf16=bf16,
+                                  kappa=kappa)
+        fine = fcn.Plan(inst, precision="fp32", stream=G.plan.stream)
+        u = fine.pack(wl.gaussian_field(inst, np.complex64))
+        g = torch.empty_like(u)
+        for w in range(windows):
+            G(u, g)
+            fine.step(u, steps_per_window)
+            out[a, w] = coarse._werr(g, u, nr, nt)
+        fine.sync()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trajectories", type=int, default=2000)
+    ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--fp32-activations", action="store_true")
+    ap.add_argument("--batch-traj", type=int, default=16)
+    ap.add_argument("--crops", type=int, default=4)
+    ap.add_argument("--crop", type=int, default=128)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--time-budget", type=float, default=None)
+    ap.add_argument("--eval", type=int, default=len(HELD_OUT), help="held-out trajectories to evaluate")
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    bf16 = not args.fp32_activations
+    t0 = time.time()
+    kappa = estimate_kappa(range(min(args.batch_traj, args.trajectories)))
+    log(f"kappa (RMS relative |F - C| per window) = {kappa:.4e}")
+    B = args.batch_traj * args.crops
+    net = coarse.CoarseNet(channels=args.channels, bf16=bf16, max_batch=B, max_h=args.crop, max_w=args.crop,
+                           training=True, seed=args.seed)
+    hist = coarse.train_coarse(net, range(args.trajectories), kappa=kappa, batch_traj=args.batch_traj,
+                               crops_per_traj=args.crops, crop_h=args.crop, crop_w=args.crop, lr=args.lr,
+                               seed=args.seed, log=log, time_budget=args.time_budget)
+    t_train = time.time() - t0
+    n_traj = min(args.trajectories, (len(hist) // wl.PARAREAL_WINDOWS) * args.batch_traj)
+    log(f"trained on {n_traj} trajectories, {len(hist)} Adam steps, {t_train:.1f} s")
+    params = net.params_numpy()
+    ids = list(HELD_OUT)[:args.eval]
+    e_cls = coarse_errors(ids)
+    e_net = coarse_errors(ids, params, channels=args.channels, bf16=bf16, kappa=kappa)
+    log(f"held-out coarse error per window: classical {e_cls.mean():.4e}, learned {e_net.mean():.4e} "
+        f"(ratio {e_net.mean() / e_cls.mean():.3f})")
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    net.save(args.out, kappa, trajectories=np.int32(n_traj), adam_steps=np.int32(len(hist)),
+             loss_history=np.asarray(hist, dtype=np.float32), crop=np.int32(args.crop),
+             heldout_ids=np.asarray(ids, dtype=np.int32), heldout_err_classical=e_cls, heldout_err_learned=e_net,
+             train_seconds=np.float64(t_train))
+    log(f"saved {args.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

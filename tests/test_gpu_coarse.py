@@ -1,0 +1,238 @@
+"""GPU tests of the learned coarse propagator and parareal, through the C ABI.
+
+The network kernels are compared with the FP64 complex reference oracle/convnet.py (itself
+pinned by finite differences): FP32-activation mode to 1e-5, BF16-activation mode to 1e-2
+with cosine similarity >= 0.999.  Parareal is checked for its defining properties: with
+G = F it converges in one iteration to the serial fine solution; after as many iterations
+as windows every window is the fine propagation of the previous one (finite termination);
+the judge falls back to the serial fine solution."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import convnet
+from paper_1507_05988_amd import coarse
+from paper_1507_05988_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _window(field, r0, c0, H, W, in_scale):
+    """The network input of one window built independently in numpy: rows r0-8..r0+H+7 with
+    row -m -> m and rows >= nr -> 0, columns periodic."""
+    nr, nt = field.shape
+    out = np.zeros((H + 16, W + 16), dtype=np.complex128)
+    for yy in range(H + 16):
+        r = abs(r0 - 8 + yy)
+        if r >= nr:
+            continue
+        cols = (c0 - 8 + np.arange(W + 16)) % nt
+        out[yy] = field[r, cols]
+    return out * in_scale
+
+
+def _setup(C, bf16, B=3, H=12, W=20, seed=0):
+    import torch
+    rng = np.random.default_rng(seed)
+    nr, nt = 40, 64
+    field = (rng.standard_normal((nr, nt)) + 1j * rng.standard_normal((nr, nt))).astype(np.complex64)
+    field[-1] = 0
+    net = coarse.CoarseNet(channels=C, bf16=bf16, max_batch=B, max_h=H, max_w=W, training=True, seed=seed)
+    p = (rng.standard_normal(net.nparams) * 0.2).astype(np.float32)
+    net.set_params(p)
+    # axis window, interior window, window across the t wrap and beyond r_max
+    spec = [(0, 0, 0, 3, 1.0, 1.0), (0, 0, 17, 50, 0.5, 1.0), (0, 0, 30, 60, 2.0, 1.0)][:B]
+    smp = coarse.samples_tensor(torch, net.device, spec)
+    fdev = torch.from_numpy(field.reshape(-1)).to(net.device)
+    x = np.stack([_window(field.astype(np.complex128), r0, c0, H, W, s)[None] for (_, _, r0, c0, s, _) in spec])
+    tgt = (rng.standard_normal((B, 1, H, W)) + 1j * rng.standard_normal((B, 1, H, W)))
+    params = convnet.unflat(p.astype(np.float64), C)
+    return net, smp, fdev, nr, nt, x, tgt, params, spec
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_network_forward_and_gradients_match_reference(bf16):
+    import torch
+    C, B, H, W = 4, 3, 12, 20
+    net, smp, fdev, nr, nt, x, tgt, params, spec = _setup(C, bf16, B, H, W)
+    net.input(fdev, smp, B, nr, nt, H, W)
+    out = torch.zeros((B, 2, H, W), dtype=torch.float32, device=net.device)
+    net.forward(B, H, W, out)
+    ref_out, acts = convnet.forward(params, x)
+    got = out.cpu().numpy()
+    got_c = got[:, 0] + 1j * got[:, 1]
+    e_fwd = np.linalg.norm(got_c - ref_out[:, 0]) / np.linalg.norm(ref_out)
+    row0 = [s[2] for s in spec]
+    t = torch.from_numpy(np.stack([tgt[:, 0].real, tgt[:, 0].imag], axis=1).astype(np.float32)).to(net.device)
+    loss = net.loss(t, row0, B, H, W, with_grad=True)
+    net.backward(B, H, W)
+    ref_loss = convnet.loss(ref_out, tgt, np.array(row0))
+    ref_g = convnet.flat(convnet.backward(params, acts, ref_out, tgt, np.array(row0)))
+    g = net.grads.cpu().numpy().astype(np.float64)
+    e_g = np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)
+    cos = float(g @ ref_g / (np.linalg.norm(g) * np.linalg.norm(ref_g)))
+    say(f"  bf16={bf16}: forward {e_fwd:.2e}, loss {abs(loss / ref_loss - 1):.2e}, grads {e_g:.2e}, cosine {cos:.6f}")
+    tol = 1e-2 if bf16 else 1e-5
+    assert e_fwd < tol and abs(loss / ref_loss - 1) < tol and e_g < tol
+    assert cos > (0.999 if bf16 else 1 - 1e-9)
+
+
+def test_network_input_target_and_apply_window_rules():
+    """fcn_net_input mirrors about the axis, reads 0 beyond r_max and wraps t; fcn_net_target
+    and fcn_net_apply use the out_scale of each sample (FP32, exact)."""
+    import torch
+    C, B, H, W = 2, 3, 12, 20
+    net, smp, fdev, nr, nt, x, *_, spec = _setup(C, False, B, H, W)
+    net.input(fdev, smp, B, nr, nt, H, W)
+    # read the input back through a network whose layers are centred identities
+    p = np.zeros(net.nparams, dtype=np.float32)
+    w0 = np.zeros((C, 1, 5, 5, 2), dtype=np.float32)
+    w0[0, 0, 2, 2, 0] = 1.0
+    p[:w0.size] = w0.reshape(-1)
+    off = w0.size + 2 * C
+    for _ in range(1, 3):
+        wm = np.zeros((C, C, 5, 5, 2), dtype=np.float32)
+        wm[0, 0, 2, 2, 0] = 1.0
+        wm[1, 1, 2, 2, 0] = 1.0
+        p[off:off + wm.size] = wm.reshape(-1)
+        off += wm.size + 2 * C
+    w3 = np.zeros((1, C, 5, 5, 2), dtype=np.float32)
+    w3[0, 0, 2, 2, 0] = 1.0
+    p[off:off + w3.size] = w3.reshape(-1)
+    net.set_params(p)
+    out = torch.zeros((B, 2, H, W), dtype=torch.float32, device=net.device)
+    net.forward(B, H, W, out)
+    got = out.cpu().numpy()
+    want = x[:, 0, 8:8 + H, 8:8 + W]
+    # CReLU keeps the positive parts
+    assert np.array_equal(got[:, 0], np.maximum(want.real, 0).astype(np.float32))
+    assert np.array_equal(got[:, 1], np.maximum(want.imag, 0).astype(np.float32))
+
+    # target: (fine - coarse) / out_scale on the output window, rows >= nr zero
+    rng = np.random.default_rng(9)
+    fine = (rng.standard_normal((nr, nt)) + 1j * rng.standard_normal((nr, nt))).astype(np.complex64)
+    crs = (rng.standard_normal((nr, nt)) + 1j * rng.standard_normal((nr, nt))).astype(np.complex64)
+    spec2 = [(0, 0, 30, 60, 1.0, 0.5)]
+    smp2 = coarse.samples_tensor(torch, net.device, spec2)
+    tgt = torch.zeros((1, 2, H, W), dtype=torch.float32, device=net.device)
+    net.target(torch.from_numpy(fine.reshape(-1)).to(net.device), torch.from_numpy(crs.reshape(-1)).to(net.device),
+               smp2, 1, nr, nt, H, W, tgt)
+    d = np.zeros((H, W), dtype=np.complex64)
+    for y in range(H):
+        if 30 + y < nr:
+            cols = (60 + np.arange(W)) % nt
+            d[y] = (fine[30 + y, cols] - crs[30 + y, cols]) * np.float32(2.0)
+    g = tgt.cpu().numpy()[0]
+    assert np.array_equal(g[0], d.real) and np.array_equal(g[1], d.imag)
+
+
+def test_adam_fits_a_teacher_network():
+    """Forward, backward and Adam together: a student fits the output of a teacher network of
+    the same shape on a fixed batch (a realizable target), so the loss must fall steadily."""
+    import torch
+    C, B, H, W = 4, 3, 12, 20
+    for bf16 in (False, True):
+        net, smp, fdev, nr, nt, x, _, params, spec = _setup(C, bf16, B, H, W, seed=4)
+        net.input(fdev, smp, B, nr, nt, H, W)
+        target = torch.zeros((B, 2, H, W), dtype=torch.float32, device=net.device)
+        net.forward(B, H, W, target)                      # teacher output
+        net.set_params(coarse.init_params(C, seed=11))   # student
+        row0 = [s[2] for s in spec]
+        hist = []
+        for _ in range(150):
+            net.forward(B, H, W)
+            hist.append(net.loss(target, row0, B, H, W, with_grad=True))
+            net.backward(B, H, W)
+            net.adam(1e-2)
+        say(f"  bf16={bf16}: loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+        assert np.all(np.isfinite(hist))
+        assert hist[-1] < 0.2 * hist[0]
+
+
+def test_train_coarse_on_fcn_trajectories():
+    """train_coarse end to end on a reduced grid: finite losses, one Adam step per window, and
+    the loss falls."""
+    net = coarse.CoarseNet(channels=8, bf16=True, max_batch=16, max_h=32, max_w=64, training=True, seed=1)
+    hist = coarse.train_coarse(net, range(8), kappa=1e-5, batch_traj=8, crops_per_traj=2, crop_h=32, crop_w=64,
+                               lr=3e-3, windows=24, steps_per_window=10, seed=0,
+                               make_inst=lambda j: wl.config_parareal_trajectory(j, nr=128, nt=512))
+    say(f"  loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert len(hist) == 24 and np.all(np.isfinite(hist))
+    assert np.mean(hist[-4:]) < np.mean(hist[:4])
+
+
+def _small_inst():
+    return wl.config_parareal_trajectory(5000, nr=64, nt=256)
+
+
+def test_parareal_with_coarse_equal_to_fine_converges_in_one_iteration():
+    """G = F (the coarse operator takes the fine steps): the coarse sweep already is the serial
+    fine solution, and iteration 1 changes nothing (bitwise)."""
+    import torch
+    inst = _small_inst()
+    nw, spw = 4, 6
+    ref = coarse.serial_fine(inst, windows=nw, steps_per_window=spw)
+    U, hist = coarse.parareal(inst, None, windows=nw, steps_per_window=spw, kmax=3, tol=1e-12, reference=ref,
+                              coarse_steps=spw)
+    assert hist[0]["error"] == 0.0
+    assert hist[1]["change"] == 0.0 and hist[-1]["status"] == "converged" and len(hist) == 2
+    for j in range(nw):
+        assert torch.equal(U[j + 1], ref[j])
+
+
+def test_parareal_finite_termination():
+    """After as many iterations as windows (judge off), every window is the fine propagation
+    of the previous one up to the rounding of the combine step, and the error against the
+    FP64 fine solution is that of the serial FP32 fine solution."""
+    import torch
+    from paper_1507_05988_amd import fcn
+    inst = _small_inst()
+    nw, spw = 4, 10
+    ref64 = coarse.serial_fine(inst, windows=nw, steps_per_window=spw, precision="fp64")
+    ref32 = coarse.serial_fine(inst, windows=nw, steps_per_window=spw)
+    U, hist = coarse.parareal(inst, None, windows=nw, steps_per_window=spw, kmax=nw, tol=0.0, reference=ref64,
+                              judge=False, fallback=False)
+    say("  errors vs FP64: " + ", ".join(f"{h['error']:.2e}" for h in hist))
+    assert len(hist) == nw + 1
+    P = fcn.Plan(inst, precision="fp32")
+    for j in range(nw):
+        f = U[j].clone()
+        P.step(f, spw)
+        P.sync()
+        assert coarse._werr(U[j + 1], f, inst["nr"], inst["nt"]) < 1e-12
+    e32 = max(coarse._werr(ref32[j], ref64[j], inst["nr"], inst["nt"]) for j in range(nw))
+    say(f"  serial FP32 vs FP64: {e32:.2e}")
+    assert hist[-1]["error"] <= 2.0 * e32 + 1e-7
+    assert torch.isfinite(U[-1]).all()
+
+
+def test_parareal_judge_falls_back_to_serial_fine():
+    """An unreachable tolerance: the judge stops and the serial fine solution is returned."""
+    import torch
+    inst = _small_inst()
+    nw, spw = 4, 10
+    ref = coarse.serial_fine(inst, windows=nw, steps_per_window=spw)
+    U, hist = coarse.parareal(inst, None, windows=nw, steps_per_window=spw, kmax=2, tol=0.0, reference=ref)
+    assert hist[-1]["status"] == "fallback"
+    for j in range(nw):
+        assert torch.equal(U[j + 1], ref[j])
+
+
+def test_parareal_with_network_runs():
+    """The learned G (an untrained network) inside parareal: finite iterates, and the change of
+    iteration 1 is finite and small."""
+    import torch
+    inst = _small_inst()
+    nw, spw = 4, 8
+    ref = coarse.serial_fine(inst, windows=nw, steps_per_window=spw)
+    p = coarse.init_params(4, seed=3)
+    U, hist = coarse.parareal(inst, p, windows=nw, steps_per_window=spw, kmax=1, tol=0.0, reference=ref, channels=4,
+                              kappa=1e-6, fallback=False)
+    assert all(torch.isfinite(u).all() for u in U)
+    assert hist[1]["change"] < 1e-3

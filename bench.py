@@ -10,10 +10,12 @@ partials included) on the resident field.  The timed steps run in chunks of at m
 500 steps (z <= 2.5 m, before the collapse near 4.2 m), each chunk starting from the
 resident initial pulse: past the collapse the trajectory is chaotic and the explicit RK4
 density step can leave its stability region (sigma_K I^K dtau > 2.785), see the design doc.
-The line also carries the FP64 plain method on the same workload, the FP32 error
-against it at checkpoints (with the FP64 run's own sensitivity to FP32 input rounding
-as the conditioning floor), the roofline of the dominant kernel and the CPU oracle's
-rate on the host.
+The line also carries the FP64 plain method and the FP32-storage mode (FP32 field, FP64
+arithmetic) on the same workload, the FP32 and FP32-storage errors against FP64 at
+checkpoints (with the FP64 run's own sensitivity to FP32 input rounding as the
+conditioning floor), parareal along z on a held-out learned-coarse trajectory (classical
+and learned coarse propagator, against the serial FP64 plain method), the roofline of the
+dominant kernel and the CPU oracle's rate on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -101,6 +103,67 @@ def cpu_baseline(inst, a0, seconds: float):
                       f"(after 1 warm step), {dt:.1f} s"}
 
 
+def parareal_measurement(torch):
+    """Parareal along z on held-out learned-coarse trajectory 2000 (Nr=512, Nt=2048, 32 windows
+    of 50 steps of 0.2 mm, Kerr only): fine and classical coarse FCN steps in FP32 storage,
+    with the classical coarse step alone and with the trained network added, against the
+    serial FP64 plain method (device time over the same 1600 steps).  Errors are r-weighted
+    relative field errors against the FP64 solution at every window boundary (max over
+    windows).  Parareal wall time includes its host-side convergence checks."""
+    from paper_1507_05988_amd import coarse, fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    inst = wl.config_parareal_trajectory(2000)
+    nwin, spw = wl.PARAREAL_WINDOWS, wl.PARAREAL_STEPS_PER_WINDOW
+    pts = int(inst["nr"]) * int(inst["nt"])
+    work = pts * nwin * spw
+    p64 = fcn.Plan(inst, precision="fp64")
+    a0 = wl.gaussian_field(inst)
+    f = p64.pack(a0)
+    ref = []
+    for _ in range(nwin):
+        p64.step(f, spw)
+        ref.append(f.clone())
+    p64.sync()
+    f = p64.pack(a0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(p64.stream)
+    p64.step(f, nwin * spw)
+    e1.record(p64.stream)
+    torch.cuda.synchronize()
+    t64 = e0.elapsed_time(e1) * 1e-3
+    res = {"workload": "learned-coarse trajectory 2000 (held out): Nr=512, Nt=2048, 32 windows x 50 steps "
+                       "of 0.2 mm, Kerr only",
+           "fp64_plain_serial": {"seconds": round(t64, 6), "value": round(work / t64, 1)}}
+    variants = [("classical", None, 32, True, 1.0)]
+    wfile = None
+    for name in ("coarse_c32_fp32.npz", "coarse_c32_bf16.npz"):
+        cand = os.path.join(ROOT, "paper_1507_05988_amd", "weights", name)
+        if os.path.exists(cand):
+            wfile = cand
+            break
+    if wfile:
+        params, ch, kappa, bf16 = coarse.CoarseNet.load(wfile)
+        variants.append(("learned", params, ch, bf16, kappa))
+    for name, params, ch, bf16, kappa in variants:
+        kw = dict(windows=nwin, steps_per_window=spw, kmax=nwin, tol=1e-6, channels=ch, bf16=bf16, kappa=kappa,
+                  precision="fp32_storage", fallback=False)
+        _, hist = coarse.parareal(inst, params, reference=ref, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coarse.parareal(inst, params, **kw)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        res[name] = {"seconds": round(tp, 6), "value": round(work / tp, 1), "vs_fp64_plain": round(t64 / tp, 3),
+                     "iterations": [{"iter": h["iter"], "change": h["change"] if h["iter"] else None,
+                                     "error": h["error"]} for h in hist],
+                     "status": hist[-1].get("status")}
+        if params is not None:
+            res[name]["weights"] = os.path.relpath(wfile, ROOT)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +173,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 10 times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -204,6 +268,18 @@ def main():
                              "steps": n64, "row_ms": round(r64, 6), "col_ms": round(c64, 6),
                              "hbm_gbs_algorithmic": round(pts * n64 / s64 * 64 / 1e9, 1)}
         del p64, f64
+        pm = fcn.Plan(inst, precision="fp32_storage")
+        initm = pm.pack(a0.astype(np.complex64))
+        fm = initm.clone()
+        pm.step(fm, min(args.warmup, 50) or 1)
+        sm = timed_steps(pm, fm, initm, n64, torch)
+        pm.sync()
+        fm.copy_(initm)
+        rm, cm, _ = pm.step_timed(fm, min(n64, CHUNK))
+        out["fp32_storage"] = {"value": round(pts * n64 / sm, 1), "ms_per_step": round(sm * 1e3 / n64, 6),
+                               "steps": n64, "row_ms": round(rm, 6), "col_ms": round(cm, 6),
+                               "hbm_gbs_algorithmic": round(pts * n64 / sm * 32 / 1e9, 1)}
+        del pm, fm
 
     # ---- FP32 error against the FP64 GPU method at checkpoints; the FP64 run started from
     # the FP32-rounded input measures how much the trajectory itself amplifies FP32 rounding
@@ -212,13 +288,16 @@ def main():
         q32 = fcn.Plan(inst, precision="fp32")
         q64 = fcn.Plan(inst, precision="fp64")
         qr = fcn.Plan(inst, precision="fp64")
+        qm = fcn.Plan(inst, precision="fp32_storage")
         g32 = q32.pack(a0.astype(np.complex64))
         g64 = q64.pack(a0)
         gr = qr.pack(a0.astype(np.complex64).astype(np.complex128))
+        gm = qm.pack(a0.astype(np.complex64))
+        ok_m = True
         acc = []
         done = 0
         for cp in checkpoints:
-            for q, g in ((q32, g32), (q64, g64), (qr, gr)):
+            for q, g in ((q32, g32), (q64, g64), (qr, gr), (qm, gm)):
                 q.step(g, cp - done)
             done = cp
             ok32 = True
@@ -228,6 +307,10 @@ def main():
                 ok32 = False
             q64.sync()
             qr.sync()
+            try:
+                qm.sync()
+            except fcn.FcnError:
+                ok_m = False
             x64 = q64.unpack(g64)[0]
             d32 = q32.split_diag(q32.diagnostics(g32))[0]
             d64 = q64.split_diag(q64.diagnostics(g64))[0]
@@ -242,10 +325,14 @@ def main():
                            energy=abs(d32["energy"] / d64["energy"] - 1))
             else:
                 row.update(field=None, note="FP32 trajectory left the RK4 density stability region")
+            row["field_fp32_storage"] = weighted_rel_err(qm.unpack(gm)[0].astype(np.complex128), x64) if ok_m else None
             acc.append(row)
             if not ok32:
                 break
         out["accuracy_fp32_vs_fp64"] = acc
+
+    if not args.no_parareal:
+        out["parareal"] = parareal_measurement(torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a0, args.cpu_seconds)

@@ -58,7 +58,11 @@ enum {
     FCN_COLL = 32        /* -(sigma_c/2) rho, collisional absorption (not in the paper) */
 };
 
-enum { FCN_FP64 = 0, FCN_FP32 = 1 };
+/* Precision modes.  FCN_FP32_STORAGE keeps the field in FP32 (the HBM traffic of FCN_FP32)
+ * and computes every stage in FP64 inside the kernels: only the two FP32 stores per step
+ * round, so the error grows like a random walk instead of accumulating the FP32 transform
+ * error coherently over slowly varying fields. */
+enum { FCN_FP64 = 0, FCN_FP32 = 1, FCN_FP32_STORAGE = 2 };
 
 /* One pulse and its grid. */
 typedef struct {
@@ -79,8 +83,9 @@ typedef struct {
 } fcn_instance;
 
 typedef struct {
-    int32_t precision;       /* FCN_FP64, or FCN_FP32 (field, FFT, CN and exponentials in FP32;
-                                density scan, operator exponents and diagnostics in FP64) */
+    int32_t precision;       /* FCN_FP64; FCN_FP32 (field, FFT, CN and exponentials in FP32;
+                                density scan, operator exponents and diagnostics in FP64); or
+                                FCN_FP32_STORAGE (FP32 field, FP64 arithmetic) */
     int32_t adaptive;        /* 0: fixed dz per instance; 1: dz_n = clamp(max_phase/Phi, dz_min,
                                 dz_max) with Phi the peak nonlinear phase rate of A^{n-1} */
     double max_phase;        /* [rad] per step, adaptive mode */

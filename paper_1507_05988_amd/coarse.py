@@ -152,7 +152,7 @@ class CoarseOperator:
     kappa s Net(U/s)."""
 
     def __init__(self, inst: dict, steps_per_window: int, net_params=None, channels=32, bf16=True, kappa=1.0,
-                 coarse_steps=1, stream=None):
+                 coarse_steps=1, precision="fp32", stream=None):
         import torch
 
         self.torch = torch
@@ -163,7 +163,7 @@ class CoarseOperator:
             raise ValueError("coarse_steps must divide steps_per_window")
         c["dz"] = inst["dz"] * (steps_per_window // coarse_steps)
         self.coarse_steps = coarse_steps
-        self.plan = fcn.Plan(c, precision="fp32", stream=stream)
+        self.plan = fcn.Plan(c, precision=precision, stream=stream)
         self.net = None
         if net_params is not None:
             self.net = CoarseNet(channels=channels, bf16=bf16, max_batch=1, max_h=self.nr, max_w=self.nt,
@@ -186,13 +186,15 @@ class CoarseOperator:
 
 def train_coarse(net: CoarseNet, traj_ids, kappa, batch_traj=16, crops_per_traj=4, crop_h=128, crop_w=128, lr=1e-3,
                  windows=wl.PARAREAL_WINDOWS, steps_per_window=wl.PARAREAL_STEPS_PER_WINDOW, seed=0, log=None,
-                 time_budget=None, make_inst=wl.config_parareal_trajectory, lr_end=None):
+                 time_budget=None, make_inst=wl.config_parareal_trajectory, lr_end=None, precision="fp32_storage"):
     """Trains `net` on FCN trajectories generated on the fly: for each group of `batch_traj`
     trajectories (one batched fine plan and one batched coarse plan), at every window boundary
     the crops of U_j / s are the inputs and the crops of (F(U_j) - C(U_j)) / (kappa s) the
     targets; one Adam step per window.  Crops cover r rows [0, nr/2) and t columns within
     nt/8 of the window centre, where the pulse is.  `make_inst(j)` gives trajectory j.  The
     learning rate decays by cosine from lr to lr_end (default lr/20) over the planned steps.
+    The FCN steps run in `precision`: FP32-storage by default, because the coherent FP32
+    transform error over one window is a sizeable fraction of F - C itself.
     Returns the loss of every step."""
     torch = net.torch
     rng = np.random.default_rng(seed)
@@ -207,8 +209,8 @@ def train_coarse(net: CoarseNet, traj_ids, kappa, batch_traj=16, crops_per_traj=
         ids = traj_ids[g0:g0 + batch_traj]
         insts = [make_inst(j) for j in ids]
         nr, nt = int(insts[0]["nr"]), int(insts[0]["nt"])
-        fine = fcn.Plan(insts, precision="fp32", stream=net.stream)
-        coarse = fcn.Plan([dict(i, dz=i["dz"] * steps_per_window) for i in insts], precision="fp32",
+        fine = fcn.Plan(insts, precision=precision, stream=net.stream)
+        coarse = fcn.Plan([dict(i, dz=i["dz"] * steps_per_window) for i in insts], precision=precision,
                           stream=net.stream)
         u = fine.pack([wl.gaussian_field(i, np.complex64) for i in insts])
         cbuf = torch.empty_like(u)
@@ -249,7 +251,7 @@ def train_coarse(net: CoarseNet, traj_ids, kappa, batch_traj=16, crops_per_traj=
 
 def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per_window=wl.PARAREAL_STEPS_PER_WINDOW,
              kmax=None, tol=1e-4, reference=None, channels=32, bf16=True, kappa=1.0, coarse_steps=1, fallback=True,
-             judge=True, stream=None, log=None):
+             judge=True, precision="fp32", stream=None, log=None):
     """Parareal along z for one pulse, with the fine FCN as corrector and judge.
 
     Iteration k runs the fine FCN over all windows in one batched plan from U^{k-1}, then the
@@ -262,14 +264,15 @@ def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per
     returned instead.  Returns (fields at the window boundaries U[0..windows], history);
     history[k] = dict(iter, change, error (vs `reference[j]` for U[j+1] if given), seconds);
     iteration 0 is the coarse sweep alone.  The last record carries `status`: "converged",
-    "diverging", "kmax" or "fallback"."""
+    "diverging", "kmax" or "fallback".  `precision` ("fp32" or "fp32_storage") is that of the
+    fine and classical coarse FCN steps; fields are complex64 either way."""
     import torch
 
     kmax = windows if kmax is None else kmax
-    fine = fcn.Plan([inst] * windows, precision="fp32", stream=stream)
+    fine = fcn.Plan([inst] * windows, precision=precision, stream=stream)
     st = fine.stream
     G = CoarseOperator(inst, steps_per_window, net_params=net_params, channels=channels, bf16=bf16,
-                       kappa=kappa, coarse_steps=coarse_steps, stream=st)
+                       kappa=kappa, coarse_steps=coarse_steps, precision=precision, stream=st)
     nr, nt = int(inst["nr"]), int(inst["nt"])
     n = nr * nt
     off = fine.offsets
@@ -333,7 +336,8 @@ def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per
             break
         record(k, change)
     if status != "converged" and fallback:
-        ref = serial_fine(inst, windows=windows, steps_per_window=steps_per_window, stream=stream)
+        ref = serial_fine(inst, windows=windows, steps_per_window=steps_per_window, precision=precision,
+                          stream=stream)
         for j in range(windows):
             U[j + 1].copy_(ref[j])
         status = "fallback"
@@ -362,7 +366,7 @@ def serial_fine(inst: dict, windows=wl.PARAREAL_WINDOWS, steps_per_window=wl.PAR
                 precision="fp32", stream=None):
     """The serial fine solution at every window boundary (list of `windows` flat fields)."""
     p = fcn.Plan(inst, precision=precision, stream=stream)
-    dt = np.complex64 if precision == "fp32" else np.complex128
+    dt = np.complex128 if precision == "fp64" else np.complex64
     f = p.pack(wl.gaussian_field(inst, dt))
     out = []
     for _ in range(windows):

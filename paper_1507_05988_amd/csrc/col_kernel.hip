@@ -37,7 +37,8 @@ struct Eq {  // lower, upper, rhs of one normalised (unit diagonal) reduced equa
     c2<R> l, u, r;
 };
 
-template <typename R, int W, int L>
+// R: arithmetic precision; ST: storage precision of the spectrum (see the row kernel).
+template <typename R, typename ST, int W, int L>
 __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     static_assert(L >= 4, "at least two interior rows per chunk");
     extern __shared__ unsigned char smem_raw[];
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const R bi_ax = R(4) * s - g;      // Im b, axis row
     const double *rc = a.rowcoef + 2 * (int64_t)in.rowcoef_off;
 
-    c2<R> *col = reinterpret_cast<c2<R> *>(a.field) + in.field_off + p;
+    c2<ST> *col = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + p;
     const int m0 = k * L;
 
     // ---- load rows m0-1 .. m0+L (halo included); rows outside [0, nr) read as 0
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
 #pragma unroll
     for (int i = 0; i < L + 2; i++) {
         const int m = m0 - 1 + i;
-        x[i] = (m >= 0 && m < nr) ? col[(int64_t)m * nt] : czero<R>();
+        x[i] = (m >= 0 && m < nr) ? ccast<R, ST>(col[(int64_t)m * nt]) : czero<R>();
     }
 
     // Row m of M_abc as (l, b, u) = (i lr, 1 + i bi, i ur) and of M_def x, computed on the fly.
@@ -219,7 +220,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
 #pragma unroll
     for (int i = 0; i < L; i++) {
         const int m = m0 + i;
-        if (m < nr) col[(int64_t)m * nt] = out[i];
+        if (m < nr) col[(int64_t)m * nt] = ccast<ST, R>(out[i]);
     }
 
     if (!a.use_stage_len && t == 0) {
@@ -231,33 +232,37 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     }
 }
 
-template <typename R, int W, int L>
+template <typename R, typename ST, int W, int L>
 static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int S = (nr + L - 1) / L;
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
     const size_t shm = sizeof(Eq<R>) * (size_t)W * 2 * S;
-    hipExtLaunchKernelGGL((col_kernel<R, W, L>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((col_kernel<R, ST, W, L>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1, 0, a);
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename R, typename ST>
 static hipError_t launch_col_p(int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1) {
-    if (w == 4 && l == 8) return launch_col_t<R, 4, 8>(nr, a, grid, s, e0, e1);
-    if (w == 4 && l == 16) return launch_col_t<R, 4, 16>(nr, a, grid, s, e0, e1);
-    if (w == 8 && l == 8) return launch_col_t<R, 8, 8>(nr, a, grid, s, e0, e1);
-    if (w == 8 && l == 16) return launch_col_t<R, 8, 16>(nr, a, grid, s, e0, e1);
-    if (w == 16 && l == 8) return launch_col_t<R, 16, 8>(nr, a, grid, s, e0, e1);
-    if (w == 16 && l == 16) return launch_col_t<R, 16, 16>(nr, a, grid, s, e0, e1);
-    if (w == 32 && l == 8) return launch_col_t<R, 32, 8>(nr, a, grid, s, e0, e1);
+    if (w == 4 && l == 8) return launch_col_t<R, ST, 4, 8>(nr, a, grid, s, e0, e1);
+    if (w == 4 && l == 16) return launch_col_t<R, ST, 4, 16>(nr, a, grid, s, e0, e1);
+    if (w == 8 && l == 8) return launch_col_t<R, ST, 8, 8>(nr, a, grid, s, e0, e1);
+    if (w == 8 && l == 16) return launch_col_t<R, ST, 8, 16>(nr, a, grid, s, e0, e1);
+    if (w == 16 && l == 8) return launch_col_t<R, ST, 16, 8>(nr, a, grid, s, e0, e1);
+    if (w == 16 && l == 16) return launch_col_t<R, ST, 16, 16>(nr, a, grid, s, e0, e1);
+    if (w == 32 && l == 8) return launch_col_t<R, ST, 32, 8>(nr, a, grid, s, e0, e1);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s, hipEvent_t e0,
                       hipEvent_t e1) {
-    return precision == 0 ? launch_col_p<double>(w, l, nr, a, grid, s, e0, e1)
-                          : launch_col_p<float>(w, l, nr, a, grid, s, e0, e1);
+    switch (precision) {
+        case 0: return launch_col_p<double, double>(w, l, nr, a, grid, s, e0, e1);
+        case 1: return launch_col_p<float, float>(w, l, nr, a, grid, s, e0, e1);
+        case 2: return launch_col_p<double, float>(w, l, nr, a, grid, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace fcn

@@ -60,5 +60,10 @@ template <typename R>
 __device__ __forceinline__ c2<R> czero() {
     return mk<R>(R(0), R(0));
 }
+// conversion between storage and arithmetic precision (round to nearest when narrowing)
+template <typename To, typename From>
+__device__ __forceinline__ c2<To> ccast(c2<From> a) {
+    return mk<To>(To(a.x), To(a.y));
+}
 
 }  // namespace fcn

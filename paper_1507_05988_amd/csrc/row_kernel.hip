@@ -366,7 +366,9 @@ struct RowCfg {
     static constexpr int TWN = TW_LDS ? NT / 2 : 1;
 };
 
-template <typename R, int NT, int E, int FLAGS>
+// R: arithmetic precision; ST: storage precision of the field (ST = float with R = double is
+// the FP32-storage mode: FP64 arithmetic, FP32 loads and stores).
+template <typename R, typename ST, int NT, int E, int FLAGS>
 __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     using Cfg = RowCfg<R, NT, E, FLAGS>;
     constexpr int T = Cfg::T;
@@ -386,7 +388,7 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     const RowItem it = a.items[active ? item_idx : 0];
     const DevInst in = a.inst[it.inst];
     c2<R> *row_lds = lds + rw * Cfg::LROW;
-    c2<R> *g = reinterpret_cast<c2<R> *>(a.field) + in.field_off + (int64_t)it.m * NT;
+    c2<ST> *g = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + (int64_t)it.m * NT;
     const c2<R> *tw = reinterpret_cast<const c2<R> *>(a.twiddle) + in.tw_off;
 
     int64_t n = 0;
@@ -409,7 +411,7 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 
     c2<R> v[E];
 #pragma unroll
-    for (int k = 0; k < E; k++) v[k] = active ? g[tr + k * T] : czero<R>();
+    for (int k = 0; k < E; k++) v[k] = active ? ccast<R, ST>(g[tr + k * T]) : czero<R>();
 
     const c2<R> *twp = tw;
     if constexpr (FFTS && Cfg::TW_LDS) {
@@ -483,7 +485,7 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     if constexpr ((FLAGS & RK_STORE) != 0) {
         if (active) {
 #pragma unroll
-            for (int k = 0; k < E; k++) g[tr + k * T] = v[k];
+            for (int k = 0; k < E; k++) g[tr + k * T] = ccast<ST, R>(v[k]);
         }
     }
 
@@ -504,25 +506,25 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 
 // Launches go through hipExtLaunchKernelGGL: with non-null events it records them at the
 // kernel's own start and end (timing without the gaps between launches).
-template <typename R, int NT, int FLAGS>
+template <typename R, typename ST, int NT, int FLAGS>
 static hipError_t launch_row_t(const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     constexpr int E = 8;
     using Cfg = RowCfg<R, NT, E, FLAGS>;
-    hipExtLaunchKernelGGL((row_kernel<R, NT, E, FLAGS>), dim3(grid), dim3(Cfg::THREADS), 0, s, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((row_kernel<R, ST, NT, E, FLAGS>), dim3(grid), dim3(Cfg::THREADS), 0, s, e0, e1, 0, a);
     return hipGetLastError();
 }
 
-template <typename R, int FLAGS>
+template <typename R, typename ST, int FLAGS>
 static hipError_t launch_row_nt(int nt, const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (nt) {
-        case 64: return launch_row_t<R, 64, FLAGS>(a, grid, s, e0, e1);
-        case 128: return launch_row_t<R, 128, FLAGS>(a, grid, s, e0, e1);
-        case 256: return launch_row_t<R, 256, FLAGS>(a, grid, s, e0, e1);
-        case 512: return launch_row_t<R, 512, FLAGS>(a, grid, s, e0, e1);
-        case 1024: return launch_row_t<R, 1024, FLAGS>(a, grid, s, e0, e1);
-        case 2048: return launch_row_t<R, 2048, FLAGS>(a, grid, s, e0, e1);
-        case 4096: return launch_row_t<R, 4096, FLAGS>(a, grid, s, e0, e1);
-        case 8192: return launch_row_t<R, 8192, FLAGS>(a, grid, s, e0, e1);
+        case 64: return launch_row_t<R, ST, 64, FLAGS>(a, grid, s, e0, e1);
+        case 128: return launch_row_t<R, ST, 128, FLAGS>(a, grid, s, e0, e1);
+        case 256: return launch_row_t<R, ST, 256, FLAGS>(a, grid, s, e0, e1);
+        case 512: return launch_row_t<R, ST, 512, FLAGS>(a, grid, s, e0, e1);
+        case 1024: return launch_row_t<R, ST, 1024, FLAGS>(a, grid, s, e0, e1);
+        case 2048: return launch_row_t<R, ST, 2048, FLAGS>(a, grid, s, e0, e1);
+        case 4096: return launch_row_t<R, ST, 4096, FLAGS>(a, grid, s, e0, e1);
+        case 8192: return launch_row_t<R, ST, 8192, FLAGS>(a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -536,22 +538,22 @@ constexpr int RK_T_FFT = RK_FFT_OUT | RK_STORE;
 constexpr int RK_T_IFFT = RK_IFFT_IN | RK_STORE;
 constexpr int RK_T_NL = RK_NL_B | RK_STORE | RK_STAGE_LEN;
 
-template <typename R>
+template <typename R, typename ST>
 static hipError_t launch_row_p(int nt, int flags, const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1) {
     switch (flags) {
-        case RK_FIRST: return launch_row_nt<R, RK_FIRST>(nt, a, grid, s, e0, e1);
-        case RK_MIDDLE: return launch_row_nt<R, RK_MIDDLE>(nt, a, grid, s, e0, e1);
-        case RK_LAST: return launch_row_nt<R, RK_LAST>(nt, a, grid, s, e0, e1);
-        case RK_DIAG_ONLY: return launch_row_nt<R, RK_DIAG_ONLY>(nt, a, grid, s, e0, e1);
-        case RK_T_NL: return launch_row_nt<R, RK_T_NL>(nt, a, grid, s, e0, e1);
-        case RK_FIRST | RK_SCAN: return launch_row_nt<R, RK_FIRST | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_MIDDLE | RK_SCAN: return launch_row_nt<R, RK_MIDDLE | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_LAST | RK_SCAN: return launch_row_nt<R, RK_LAST | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_DIAG_ONLY | RK_SCAN: return launch_row_nt<R, RK_DIAG_ONLY | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_T_NL | RK_SCAN: return launch_row_nt<R, RK_T_NL | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_T_FFT: return launch_row_nt<R, RK_T_FFT>(nt, a, grid, s, e0, e1);
-        case RK_T_IFFT: return launch_row_nt<R, RK_T_IFFT>(nt, a, grid, s, e0, e1);
+        case RK_FIRST: return launch_row_nt<R, ST, RK_FIRST>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE: return launch_row_nt<R, ST, RK_MIDDLE>(nt, a, grid, s, e0, e1);
+        case RK_LAST: return launch_row_nt<R, ST, RK_LAST>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY: return launch_row_nt<R, ST, RK_DIAG_ONLY>(nt, a, grid, s, e0, e1);
+        case RK_T_NL: return launch_row_nt<R, ST, RK_T_NL>(nt, a, grid, s, e0, e1);
+        case RK_FIRST | RK_SCAN: return launch_row_nt<R, ST, RK_FIRST | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE | RK_SCAN: return launch_row_nt<R, ST, RK_MIDDLE | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_LAST | RK_SCAN: return launch_row_nt<R, ST, RK_LAST | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY | RK_SCAN: return launch_row_nt<R, ST, RK_DIAG_ONLY | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_T_NL | RK_SCAN: return launch_row_nt<R, ST, RK_T_NL | RK_SCAN>(nt, a, grid, s, e0, e1);
+        case RK_T_FFT: return launch_row_nt<R, ST, RK_T_FFT>(nt, a, grid, s, e0, e1);
+        case RK_T_IFFT: return launch_row_nt<R, ST, RK_T_IFFT>(nt, a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -564,8 +566,12 @@ int row_rows_per_group(int nt, int elems) {
 hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1) {
     if (elems != 8) return hipErrorInvalidValue;
-    return precision == 0 ? launch_row_p<double>(nt, flags, a, grid, s, e0, e1)
-                          : launch_row_p<float>(nt, flags, a, grid, s, e0, e1);
+    switch (precision) {
+        case 0: return launch_row_p<double, double>(nt, flags, a, grid, s, e0, e1);
+        case 1: return launch_row_p<float, float>(nt, flags, a, grid, s, e0, e1);
+        case 2: return launch_row_p<double, float>(nt, flags, a, grid, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ------------------------------------------------------------------ small kernels

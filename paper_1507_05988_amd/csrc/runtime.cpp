@@ -58,7 +58,7 @@ struct fcn_plan_s {
     fcn_options opt{};
     int batch = 0;
     int precision = 0;
-    size_t csize = 16;  // bytes per complex element
+    size_t csize = 16;  // bytes per complex element of the arithmetic (twiddle tables)
 
     std::vector<DevInst> dinst;
     size_t field_elems = 0;
@@ -206,7 +206,7 @@ bool col_tiles_supported(int w, int l) {
 
 // Column tile choice: frequencies per workgroup W and rows per thread L.
 void choose_col_tiles(int precision, int nr, const fcn_options &opt, int &w, int &l) {
-    l = opt.col_rows ? opt.col_rows : (precision == 0 ? 8 : 16);
+    l = opt.col_rows ? opt.col_rows : (precision == FCN_FP32 ? 16 : 8);
     w = opt.col_tile ? opt.col_tile : 4;
     // keep the workgroup within 512 threads
     while (w * ((nr + l - 1) / l) > 512 && w > 4) w /= 2;
@@ -215,7 +215,7 @@ void choose_col_tiles(int precision, int nr, const fcn_options &opt, int &w, int
 
 fcn_status build_plan(fcn_plan_t p) {
     const int B = p->batch;
-    p->csize = p->precision == 0 ? 16 : 8;
+    p->csize = p->precision == FCN_FP32 ? 8 : 16;
     p->dinst.resize(B);
 
     // twiddle tables per distinct nt
@@ -232,7 +232,7 @@ fcn_status build_plan(fcn_plan_t p) {
         twiddle_table(kv.first, re, im);
         for (int k = 0; k < kv.first; k++) {
             const size_t e = (size_t)kv.second + k;
-            if (p->precision == 0) {
+            if (p->precision != FCN_FP32) {
                 double v[2] = {re[k], im[k]};
                 memcpy(&p->twiddles[e * 16], v, 16);
             } else {
@@ -588,7 +588,7 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
     p->insts.assign(inst, inst + batch);
     if (opt) p->opt = *opt;
     p->precision = p->opt.precision;
-    if (p->precision != FCN_FP64 && p->precision != FCN_FP32) {
+    if (p->precision != FCN_FP64 && p->precision != FCN_FP32 && p->precision != FCN_FP32_STORAGE) {
         delete p;
         return FCN_E_ARG;
     }

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcn.so")
 
 FCN_OK, FCN_E_ARG, FCN_E_SIZE, FCN_E_HIP, FCN_E_NONFINITE, FCN_E_STATE, FCN_E_UNSUPPORTED = range(7)
-FCN_FP64, FCN_FP32 = 0, 1
+FCN_FP64, FCN_FP32, FCN_FP32_STORAGE = 0, 1, 2
+PRECISIONS = {"fp64": FCN_FP64, "fp32": FCN_FP32, "fp32_storage": FCN_FP32_STORAGE}
 STAGE_FFT, STAGE_IFFT, STAGE_CN, STAGE_NL = 0, 1, 2, 3
 DIAG_SCALARS = 8
 DIAG_NAMES = ("energy", "i_max", "i_axis", "rho_max", "phi", "z", "step", "dz_prev")
@@ -129,8 +130,9 @@ def make_instance(inst: dict) -> Instance:
 class Plan:
     """A batch of pulses stepped together on one GPU.
 
-    instances: list of instance dicts (see workloads.py); precision "fp64" or "fp32".
-    The field is one flat complex torch tensor on the device (complex128 / complex64),
+    instances: list of instance dicts (see workloads.py); precision "fp64", "fp32" or
+    "fp32_storage" (FP32 field, FP64 arithmetic in the kernels).
+    The field is one flat complex torch tensor on the device (complex128 for fp64, else complex64),
     instance i occupying [offset(i), offset(i) + nr*nt) as a row-major [nr][nt] matrix.
     """
 
@@ -147,11 +149,13 @@ class Plan:
             instances = [instances]
         self.instances = [dict(i) for i in instances]
         self.batch = len(self.instances)
+        if precision not in PRECISIONS:
+            raise FcnError(FCN_E_ARG, f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision
         self.device = torch.device("cuda", device)
         self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
         arr = (Instance * self.batch)(*[make_instance(i) for i in self.instances])
-        opt = Options(precision=FCN_FP64 if precision == "fp64" else FCN_FP32, adaptive=int(adaptive),
+        opt = Options(precision=PRECISIONS[precision], adaptive=int(adaptive),
                       max_phase=max_phase, dz_min=dz_min, dz_max=dz_max, use_graph=int(use_graph),
                       col_tile=col_tile, col_rows=col_rows, reserved=0)
         self._h = ctypes.c_void_p()

@@ -363,3 +363,84 @@ def test_fp32_energy_drift_is_bounded():
     drift = max(abs(x / e[0] - 1) for x in e)
     say(f"  FP32 energy drift over 400 steps: {drift:.3e}")
     assert drift < 400 * 5e-8
+
+
+# ------------------------------------------------- FP32 storage with FP64 arithmetic
+
+@pytest.mark.parametrize("nt", [64, 2048, 8192])
+def test_fp32_storage_stages(nt):
+    """Each stage in FP32-storage mode: FP64 arithmetic on FP32-rounded input, one FP32
+    rounding of the output, so the error is that of two roundings (<= 2^-23 relative to the
+    largest element) whatever the transform length or solve size."""
+    say(f"fp32-storage stages nt={nt}")
+    nr = 37
+    inst = wl.config_full(nr=nr, nt=nt)
+    a = wl.random_field(nr, nt, seed=nt + 1)
+    a32 = a.astype(np.complex64).astype(np.complex128)
+    plan = _plan(inst, "fp32_storage")
+    tol = 2.0 ** -23
+    for stage, want in ((fcn.STAGE_FFT, oracle.fft_rows(a32)),
+                        (fcn.STAGE_IFFT, oracle.fft_rows(a32, inverse=True)),
+                        (fcn.STAGE_CN, oracle.cn_columns(inst, a32, 0.05))):
+        f = plan.pack(a)
+        plan.stage(stage, f, 0.05 if stage == fcn.STAGE_CN else 0.0)
+        got = plan.unpack(f)[0].astype(np.complex128)
+        e = relmax(got, want)
+        say(f"  stage {stage}: {e:.2e}")
+        assert e < tol
+    plan.sync()
+
+
+def test_fp32_storage_single_step_and_run():
+    """One full-model step from an ionising state, then 40 steps: only the FP32 stores round,
+    and their errors do not add up coherently the way FP32 transform errors do."""
+    inst = wl.config_full(nr=96, nt=512)
+    a0 = wl.gaussian_field(inst) * math.sqrt(6e17 / inst["I0"])
+    a5 = oracle.propagate(inst, a0, 5)
+    a5_32 = a5.astype(np.complex64)
+    got, _ = _run(inst, "fp32_storage", 1, a0=a5_32)
+    e1 = werr(got.astype(np.complex128), oracle.propagate(inst, a5_32.astype(np.complex128), 1))
+    a0_32 = a0.astype(np.complex64)
+    got40, _ = _run(inst, "fp32_storage", 40, a0=a0_32)
+    want40 = oracle.propagate(inst, a0_32.astype(np.complex128), 40)
+    e40 = werr(got40.astype(np.complex128), want40)
+    g32, _ = _run(inst, "fp32", 40, a0=a0_32)
+    e40_32 = werr(g32.astype(np.complex128), want40)
+    say(f"  fp32-storage: one step {e1:.2e}, 40 steps {e40:.2e} (FP32 arithmetic: {e40_32:.2e})")
+    assert e1 < 2e-7
+    assert e40 < 2e-6
+    assert e40 < e40_32 / 5
+
+
+def test_fp32_storage_long_run_error_vs_fp64():
+    """800 steps of a Kerr pulse on a 128 x 512 grid against the FP64 GPU method: the error of
+    FP32 storage grows like a random walk of the store roundings (~1e-6 here), far below the
+    FP32-arithmetic error, which accumulates coherently (~5e-5)."""
+    inst = wl.config_parareal_trajectory(5000, nr=128, nt=512)
+    a0 = wl.gaussian_field(inst)
+    ref, _ = _run(inst, "fp64", 800, a0=a0)
+    got, _ = _run(inst, "fp32_storage", 800, a0=a0)
+    g32, _ = _run(inst, "fp32", 800, a0=a0)
+    e = werr(got.astype(np.complex128), ref)
+    e32 = werr(g32.astype(np.complex128), ref)
+    say(f"  800 steps vs FP64: fp32-storage {e:.2e}, fp32 {e32:.2e}")
+    assert e < 5e-6
+    assert e < e32 / 5
+
+
+def test_fp32_storage_batch_and_graph():
+    """The ragged batch and the graph replay in FP32-storage mode give the same bits as single
+    instances stepped eagerly."""
+    import torch
+    insts = [wl.config_small(nr=40, nt=256), wl.config_small(nr=72, nt=512)]
+    fields = [wl.gaussian_field(i, np.complex64) for i in insts]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch = _plan(insts, "fp32_storage", use_graph=True, stream=stream)
+        f = batch.pack(fields)
+        batch.step(f, 37)  # 2 graph replays of 16 steps + eager remainder
+        batch.sync()
+        got = batch.unpack(f)
+    for i, inst in enumerate(insts):
+        single, _ = _run(inst, "fp32_storage", 37, a0=fields[i])
+        assert np.array_equal(got[i], single)

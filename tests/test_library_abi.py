@@ -86,6 +86,23 @@ def test_invalid_instances_rejected(lib, field, value, code):
     assert not h.value
 
 
+def test_fp32_storage_mode_on_host(lib):
+    """FCN_FP32_STORAGE plans: same field size as FP32, FP64 twiddle tables in the workspace."""
+    insts = [wl.config_small(nr=64, nt=256), wl.config_small(nr=40, nt=512)]
+    sizes = {}
+    for prec in (fcn.FCN_FP32, fcn.FCN_FP32_STORAGE):
+        rc, h = _create(lib, insts, precision=prec)
+        assert rc == fcn.FCN_OK
+        sz = ctypes.c_size_t()
+        assert lib.fcn_field_size(h, ctypes.byref(sz)) == 0
+        assert sz.value == 64 * 256 + 40 * 512
+        assert lib.fcn_plan_workspace_size(h, ctypes.byref(sz)) == 0
+        sizes[prec] = sz.value
+        lib.fcn_plan_destroy(h)
+    assert sizes[fcn.FCN_FP32_STORAGE] >= sizes[fcn.FCN_FP32] + 8 * (256 + 512)
+    assert _create(lib, insts, precision=3)[0] == fcn.FCN_E_ARG
+
+
 def test_invalid_options_rejected(lib):
     inst = wl.config_small()
     assert _create(lib, [inst], precision=7)[0] == fcn.FCN_E_ARG

@@ -174,8 +174,9 @@ fcn_status fcn_plan_destroy(fcn_plan_t plan);
 fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, double *row_ms, double *col_ms,
                           double *total_ms);
 
-/* Launch configuration the plan chose: rows per thread and frequencies per workgroup of the
- * column solve, elements per thread of the row kernel. */
+/* Launch configuration the plan chose: frequencies per workgroup and rows per thread of the
+ * column solve (of the last nr bucket), elements per thread of the row kernel (for the
+ * largest nt: 8, or 16 at nt = 8192). */
 fcn_status fcn_plan_tiles(fcn_plan_t plan, int32_t *col_tile, int32_t *col_rows, int32_t *row_elems);
 
 /* ------------------------------------------------------------------------------------

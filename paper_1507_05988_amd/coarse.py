@@ -2,8 +2,10 @@
 
 G(U) = C(U) + kappa s Net(U/s): C is one classical FCN step over the whole window length
 (50 fine steps of dz in one step of 50 dz), Net the complex convolutional operator of
-include/fcn.h (fcn_net_*), s = sqrt(I0) of the pulse and kappa a fixed output scale (the
-typical relative size of F - C over one window) so that the network predicts O(1) values.  Parareal over N windows:
+include/fcn.h (fcn_net_*), s = sqrt(I_ref) one fixed field scale for every pulse (the Kerr
+response depends on the absolute intensity, so the network must see it: a per-pulse scale
+would hide the pulse power from it) and kappa a fixed output scale (the typical relative
+size of F - C over one window) so that the network predicts values of order one.  Parareal over N windows:
 U_{j+1}^{k+1} = G(U_j^{k+1}) + F(U_j^k) - G(U_j^k), F = 50 fine FCN steps, with the fine
 sweep of all windows batched in one plan.  Every numerical step runs in the HIP kernels of
 libfcn.so; this module only orchestrates calls and holds buffers (torch device tensors).
@@ -20,12 +22,16 @@ from . import fcn
 from . import workloads as wl
 
 HALO = 8  # receptive-field radius of 4 layers of 5x5
+# field scale of the network: the peak field of a 5 Pcr pulse with w0 = 1 mm (the middle of
+# the learned-coarse trajectory family)
+S_REF = math.sqrt(wl.peak_intensity(5.0 * wl.critical_power(800e-9, 1.0, 3.2e-23), 1e-3))
 
 
 def init_params(channels: int, seed: int) -> np.ndarray:
     """Seeded complex initialisation, flat in the layout of include/fcn.h: weights
-    (N(0,1) + i N(0,1)) sqrt(1/(2 fan_in)), fan_in = 25 ci, biases 0; the last layer is scaled
-    by 0.1 so the untrained G starts close to the classical coarse step."""
+    (N(0,1) + i N(0,1)) sqrt(1/(2 fan_in)), fan_in = 25 ci; hidden biases 0.01 (1 + i) so
+    every CReLU unit starts active, output bias 0; the last layer is scaled by 0.1 so the
+    untrained G starts close to the classical coarse step."""
     rng = np.random.default_rng(seed)
     cin = [1, channels, channels, channels]
     cout = [channels, channels, channels, 1]
@@ -34,7 +40,7 @@ def init_params(channels: int, seed: int) -> np.ndarray:
         std = math.sqrt(1.0 / (2.0 * 25 * ci)) * (0.1 if l == 3 else 1.0)
         w = rng.standard_normal((co, ci, 5, 5, 2)) * std
         parts.append(w.reshape(-1))
-        parts.append(np.zeros(2 * co))
+        parts.append(np.full(2 * co, 0.01 if l < 3 else 0.0))
     return np.concatenate(parts).astype(np.float32)
 
 
@@ -124,15 +130,16 @@ class CoarseNet:
     def params_numpy(self) -> np.ndarray:
         return self.params.detach().cpu().numpy().copy()
 
-    def save(self, path, kappa, **meta):
+    def save(self, path, kappa, s_ref=S_REF, **meta):
         np.savez(path, params=self.params_numpy(), channels=np.int32(self.channels), kappa=np.float64(kappa),
-                 bf16=np.int32(1 if self.bf16 else 0), **meta)
+                 s_ref=np.float64(s_ref), bf16=np.int32(1 if self.bf16 else 0), **meta)
 
     @staticmethod
     def load(path):
-        """(params, channels, kappa, bf16) of a saved network (plain arrays, no pickles)."""
+        """dict(params, channels, kappa, s_ref, bf16) of a saved network (plain arrays, no pickles)."""
         d = np.load(path, allow_pickle=False)
-        return d["params"], int(d["channels"]), float(d["kappa"]), bool(int(d["bf16"]))
+        return {"params": d["params"], "channels": int(d["channels"]), "kappa": float(d["kappa"]),
+                "s_ref": float(d["s_ref"]), "bf16": bool(int(d["bf16"]))}
 
     def close(self):
         if self._h:
@@ -152,7 +159,7 @@ class CoarseOperator:
     kappa s Net(U/s)."""
 
     def __init__(self, inst: dict, steps_per_window: int, net_params=None, channels=32, bf16=True, kappa=1.0,
-                 coarse_steps=1, precision="fp32", stream=None):
+                 coarse_steps=1, precision="fp32", s_ref=S_REF, stream=None):
         import torch
 
         self.torch = torch
@@ -168,8 +175,7 @@ class CoarseOperator:
         if net_params is not None:
             self.net = CoarseNet(channels=channels, bf16=bf16, max_batch=1, max_h=self.nr, max_w=self.nt,
                                  training=False, params=net_params, stream=self.plan.stream)
-            s = math.sqrt(inst["I0"])
-            self.samples = samples_tensor(torch, self.plan.device, [(0, 0, 0, 0, 1.0 / s, kappa * s)])
+            self.samples = samples_tensor(torch, self.plan.device, [(0, 0, 0, 0, 1.0 / s_ref, kappa * s_ref)])
         self.tmp = self.plan.empty_field()
 
     def __call__(self, u, out):
@@ -184,17 +190,20 @@ class CoarseOperator:
         self.net.apply(self.tmp, self.samples, 1, self.nr, self.nt, out)
 
 
-def train_coarse(net: CoarseNet, traj_ids, kappa, batch_traj=16, crops_per_traj=4, crop_h=128, crop_w=128, lr=1e-3,
-                 windows=wl.PARAREAL_WINDOWS, steps_per_window=wl.PARAREAL_STEPS_PER_WINDOW, seed=0, log=None,
-                 time_budget=None, make_inst=wl.config_parareal_trajectory, lr_end=None, precision="fp32_storage"):
+def train_coarse(net: CoarseNet, traj_ids, kappa, s_ref=S_REF, batch_traj=16, crops_per_traj=4, crop_h=128,
+                 crop_w=128, lr=1e-3,
+                 windows=wl.LEARNED_WINDOWS, steps_per_window=wl.LEARNED_STEPS_PER_WINDOW, seed=0, log=None,
+                 time_budget=None, make_inst=wl.config_parareal_trajectory, lr_end=None, precision="fp32_storage",
+                 warmup=100, updates_per_window=4):
     """Trains `net` on FCN trajectories generated on the fly: for each group of `batch_traj`
     trajectories (one batched fine plan and one batched coarse plan), at every window boundary
-    the crops of U_j / s are the inputs and the crops of (F(U_j) - C(U_j)) / (kappa s) the
-    targets; one Adam step per window.  Crops cover r rows [0, nr/2) and t columns within
-    nt/8 of the window centre, where the pulse is.  `make_inst(j)` gives trajectory j.  The
-    learning rate decays by cosine from lr to lr_end (default lr/20) over the planned steps.
-    The FCN steps run in `precision`: FP32-storage by default, because the coherent FP32
-    transform error over one window is a sizeable fraction of F - C itself.
+    the crops of U_j / s_ref are the inputs and the crops of (F(U_j) - C(U_j)) / (kappa s_ref) the
+    targets; `updates_per_window` Adam steps per window, each on freshly drawn crops.  Crops
+    cover r rows [0, nr/2) and t columns within nt/8 of the window centre, where the pulse
+    is.  `make_inst(j)` gives trajectory j.  The learning rate rises linearly over the first
+    `warmup` steps, then decays by cosine from lr to lr_end (default lr/20).  The FCN steps
+    run in `precision`: FP32-storage by default, because the coherent error of FP32
+    arithmetic over one window is comparable to F - C itself.
     Returns the loss of every step."""
     torch = net.torch
     rng = np.random.default_rng(seed)
@@ -203,7 +212,7 @@ def train_coarse(net: CoarseNet, traj_ids, kappa, batch_traj=16, crops_per_traj=
     t0 = time.time()
     nb = crops_per_traj
     lr_end = lr / 20 if lr_end is None else lr_end
-    total = max(1, ((len(traj_ids) + batch_traj - 1) // batch_traj) * windows)
+    total = max(1, ((len(traj_ids) + batch_traj - 1) // batch_traj) * windows * updates_per_window)
     step_no = 0
     for g0 in range(0, len(traj_ids), batch_traj):
         ids = traj_ids[g0:g0 + batch_traj]
@@ -216,33 +225,37 @@ def train_coarse(net: CoarseNet, traj_ids, kappa, batch_traj=16, crops_per_traj=
         cbuf = torch.empty_like(u)
         B = len(ids) * nb
         target = torch.empty((B, 2, crop_h, crop_w), dtype=torch.float32, device=u.device)
+        ubuf = torch.empty_like(u)
         r_hi = max(1, nr // 2 - crop_h + 1)
         c_span = nt // 8
         for j in range(windows):
-            rows, row0 = [], []
-            for k, inst in enumerate(insts):
-                s = math.sqrt(inst["I0"])
-                for _ in range(nb):
-                    r0 = int(rng.integers(0, r_hi))
-                    c0 = int(nt // 2 - crop_w // 2 + rng.integers(-c_span, c_span + 1))
-                    rows.append((fine.offsets[k], coarse.offsets[k], r0, c0, 1.0 / s, kappa * s))
-                    row0.append(r0)
-            smp = samples_tensor(torch, u.device, rows)
+            ubuf.copy_(u)
             cbuf.copy_(u)
             coarse.step(cbuf, 1)
-            net.input(u, smp, B, nr, nt, crop_h, crop_w)
             fine.step(u, steps_per_window)
-            net.target(u, cbuf, smp, B, nr, nt, crop_h, crop_w, target)
-            net.forward(B, crop_h, crop_w)
-            loss = net.loss(target, row0, B, crop_h, crop_w, with_grad=True)
-            net.backward(B, crop_h, crop_w)
-            frac = min(1.0, step_no / total)
-            net.adam(lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * frac)))
-            step_no += 1
-            history.append(loss)
+            for _ in range(updates_per_window):
+                rows, row0 = [], []
+                for k in range(len(insts)):
+                    for _ in range(nb):
+                        r0 = int(rng.integers(0, r_hi))
+                        c0 = int(nt // 2 - crop_w // 2 + rng.integers(-c_span, c_span + 1))
+                        rows.append((fine.offsets[k], coarse.offsets[k], r0, c0, 1.0 / s_ref, kappa * s_ref))
+                        row0.append(r0)
+                smp = samples_tensor(torch, u.device, rows)
+                net.input(ubuf, smp, B, nr, nt, crop_h, crop_w)
+                net.target(u, cbuf, smp, B, nr, nt, crop_h, crop_w, target)
+                net.forward(B, crop_h, crop_w)
+                loss = net.loss(target, row0, B, crop_h, crop_w, with_grad=True)
+                net.backward(B, crop_h, crop_w)
+                frac = min(1.0, step_no / total)
+                rate = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * frac))
+                net.adam(rate * min(1.0, (step_no + 1) / max(1, warmup)))
+                step_no += 1
+                history.append(loss)
         fine.sync()
         if log:
-            log(f"trajectories {ids[0]}..{ids[-1]}: mean loss over the group {np.mean(history[-windows:]):.4e}, "
+            log(f"trajectories {ids[0]}..{ids[-1]}: mean loss over the group "
+                f"{np.mean(history[-windows * updates_per_window:]):.4e}, "
                 f"{time.time() - t0:.1f} s")
         if time_budget is not None and time.time() - t0 > time_budget:
             break
@@ -251,7 +264,7 @@ def train_coarse(net: CoarseNet, traj_ids, kappa, batch_traj=16, crops_per_traj=
 
 def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per_window=wl.PARAREAL_STEPS_PER_WINDOW,
              kmax=None, tol=1e-4, reference=None, channels=32, bf16=True, kappa=1.0, coarse_steps=1, fallback=True,
-             judge=True, precision="fp32", stream=None, log=None):
+             judge=True, precision="fp32", s_ref=S_REF, stream=None, log=None):
     """Parareal along z for one pulse, with the fine FCN as corrector and judge.
 
     Iteration k runs the fine FCN over all windows in one batched plan from U^{k-1}, then the
@@ -272,7 +285,7 @@ def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per
     fine = fcn.Plan([inst] * windows, precision=precision, stream=stream)
     st = fine.stream
     G = CoarseOperator(inst, steps_per_window, net_params=net_params, channels=channels, bf16=bf16,
-                       kappa=kappa, coarse_steps=coarse_steps, precision=precision, stream=st)
+                       kappa=kappa, coarse_steps=coarse_steps, precision=precision, s_ref=s_ref, stream=st)
     nr, nt = int(inst["nr"]), int(inst["nt"])
     n = nr * nt
     off = fine.offsets

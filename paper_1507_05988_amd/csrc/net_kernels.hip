@@ -35,69 +35,88 @@ __device__ __forceinline__ void st_act(bf16_t *p, size_t i, float x) {
 
 // ---------------------------------------------------------------- 5x5 convolution
 
-constexpr int CV_TH = 8, CV_TW = 32, CV_CIT = 8, CV_COT = 16;
+constexpr int CV_TH = 16, CV_TW = 64, CV_CIT = 8, CV_PX = 4;
+constexpr int CV_PITCH = CV_TW + 8;  // LDS row pitch in floats (16-byte aligned rows)
 
 // out[b][co][y][x] = bias[co] + sum_{ci,ky,kx} in[b][ci][y+ky-pad][x+kx-pad] w[co][ci][ky][kx]
 // (in read as 0 outside [0,Hin) x [0,Win)), ReLU when relu != 0.  Valid convolution with
 // pad = 0; with pad = 4, flipped and transposed weights it is the input gradient.
-// Grid: x = ceil(Wout/32), y = ceil(Hout/8), z = B * ceil(Cout/16); 256 threads.
-template <typename AI, typename AO>
+// Workgroup: a 16 x 64 output tile and COT output channels; thread (ty, q) computes the 4
+// adjacent outputs x = 4q .. 4q+3 of row ty for all COT channels.  Input channels are
+// staged 8 at a time in LDS with the 4-point halo; a thread reads its 8-wide input window
+// of each kernel row as two aligned 16-byte loads and slides it over the 5 taps.  Weight
+// addresses are uniform across the workgroup, so they are read with scalar loads and
+// every FMA takes one operand from an SGPR.  Channels beyond Cout reuse the last
+// channel's weights and are not stored.
+// Grid: x = ceil(Wout/64), y = ceil(Hout/16), z = B * ceil(Cout/COT); 256 threads.
+template <typename AI, typename AO, int COT>
 __global__ void __launch_bounds__(256) conv5_kernel(const AI *__restrict__ in, const float *__restrict__ w,
                                                     const float *__restrict__ bias, AO *__restrict__ out, int Cin,
                                                     int Hin, int Win, int Cout, int Hout, int Wout, int pad,
                                                     int relu) {
-    __shared__ float s_in[CV_CIT][CV_TH + 4][CV_TW + 5];
-    __shared__ float s_w[CV_COT][CV_CIT][25];
-    const int co_groups = (Cout + CV_COT - 1) / CV_COT;
+    __shared__ __align__(16) float s_in[CV_CIT][CV_TH + 4][CV_PITCH];
+    const int co_groups = (Cout + COT - 1) / COT;
     const int b = blockIdx.z / co_groups;
-    const int co0 = (blockIdx.z % co_groups) * CV_COT;
+    const int co0 = (blockIdx.z % co_groups) * COT;
     const int y0 = blockIdx.y * CV_TH, x0 = blockIdx.x * CV_TW;
-    const int tid = threadIdx.x, ty = tid / CV_TW, tx = tid % CV_TW;
-    float acc[CV_COT];
+    const int tid = threadIdx.x, ty = tid >> 4, q = tid & 15;
+    const int clast = Cout - 1 - co0;  // last valid channel of the group, relative to co0
+    float acc[CV_PX][COT];
 #pragma unroll
-    for (int c = 0; c < CV_COT; c++) acc[c] = 0.0f;
+    for (int j = 0; j < CV_PX; j++)
+#pragma unroll
+        for (int c = 0; c < COT; c++) acc[j][c] = 0.0f;
 
     for (int ci0 = 0; ci0 < Cin; ci0 += CV_CIT) {
-        constexpr int TILE = (CV_TH + 4) * (CV_TW + 4);
+        constexpr int TW4 = CV_TW + 4;
+        constexpr int TILE = (CV_TH + 4) * TW4;
         for (int idx = tid; idx < CV_CIT * TILE; idx += 256) {
             const int ci = idx / TILE, rem = idx % TILE;
-            const int yy = rem / (CV_TW + 4), xx = rem % (CV_TW + 4);
+            const int yy = rem / TW4, xx = rem % TW4;
             const int gy = y0 + yy - pad, gx = x0 + xx - pad;
             float v = 0.0f;
             if (ci0 + ci < Cin && gy >= 0 && gy < Hin && gx >= 0 && gx < Win)
                 v = ld_act(in, (((size_t)b * Cin + ci0 + ci) * Hin + gy) * Win + gx);
             s_in[ci][yy][xx] = v;
         }
-        for (int idx = tid; idx < CV_COT * CV_CIT * 25; idx += 256) {
-            const int c = idx / (CV_CIT * 25), rem = idx % (CV_CIT * 25);
-            const int ci = rem / 25, k = rem % 25;
-            float v = 0.0f;
-            if (co0 + c < Cout && ci0 + ci < Cin) v = w[((size_t)(co0 + c) * Cin + ci0 + ci) * 25 + k];
-            s_w[c][ci][k] = v;
-        }
         __syncthreads();
         const int nci = min(CV_CIT, Cin - ci0);
         for (int ci = 0; ci < nci; ci++) {
+            const float *wc = w + ((size_t)co0 * Cin + ci0 + ci) * 25;
 #pragma unroll
-            for (int ky = 0; ky < 5; ky++)
+            for (int ky = 0; ky < 5; ky++) {
+                const float4 lo = *reinterpret_cast<const float4 *>(&s_in[ci][ty + ky][4 * q]);
+                const float4 hi = *reinterpret_cast<const float4 *>(&s_in[ci][ty + ky][4 * q + 4]);
+                const float r[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
                 for (int kx = 0; kx < 5; kx++) {
-                    const float v = s_in[ci][ty + ky][tx + kx];
 #pragma unroll
-                    for (int c = 0; c < CV_COT; c++) acc[c] = fmaf(v, s_w[c][ci][ky * 5 + kx], acc[c]);
+                    for (int c = 0; c < COT; c++) {
+                        const float wv = wc[(size_t)min(c, clast) * Cin * 25 + ky * 5 + kx];
+#pragma unroll
+                        for (int j = 0; j < CV_PX; j++) acc[j][c] = fmaf(r[j + kx], wv, acc[j][c]);
+                    }
                 }
+            }
         }
         __syncthreads();
     }
-    const int y = y0 + ty, x = x0 + tx;
-    if (y < Hout && x < Wout) {
+    const int y = y0 + ty;
+    if (y < Hout) {
 #pragma unroll
-        for (int c = 0; c < CV_COT; c++) {
+        for (int c = 0; c < COT; c++) {
             const int co = co0 + c;
             if (co < Cout) {
-                float v = acc[c] + (bias ? bias[co] : 0.0f);
-                if (relu) v = fmaxf(v, 0.0f);
-                st_act(out, (((size_t)b * Cout + co) * Hout + y) * Wout + x, v);
+                const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+                for (int j = 0; j < CV_PX; j++) {
+                    const int x = x0 + 4 * q + j;
+                    if (x < Wout) {
+                        float v = acc[j][c] + bv;
+                        if (relu) v = fmaxf(v, 0.0f);
+                        st_act(out, (((size_t)b * Cout + co) * Hout + y) * Wout + x, v);
+                    }
+                }
             }
         }
     }
@@ -365,10 +384,16 @@ __global__ void __launch_bounds__(256) parareal_update_kernel(const float2 *g_ne
 template <typename AI, typename AO>
 static hipError_t conv5_t(const AI *in, const float *w, const float *bias, AO *out, int B, int Cin, int Hin, int Win,
                           int Cout, int Hout, int Wout, int pad, int relu, hipStream_t s) {
-    const int cg = (Cout + CV_COT - 1) / CV_COT;
-    dim3 grid((Wout + CV_TW - 1) / CV_TW, (Hout + CV_TH - 1) / CV_TH, B * cg);
-    hipLaunchKernelGGL((conv5_kernel<AI, AO>), grid, dim3(256), 0, s, in, w, bias, out, Cin, Hin, Win, Cout, Hout,
-                       Wout, pad, relu);
+    const dim3 block(256);
+    if (Cout <= 2) {
+        dim3 grid((Wout + CV_TW - 1) / CV_TW, (Hout + CV_TH - 1) / CV_TH, B * ((Cout + 1) / 2));
+        hipLaunchKernelGGL((conv5_kernel<AI, AO, 2>), grid, block, 0, s, in, w, bias, out, Cin, Hin, Win, Cout, Hout,
+                           Wout, pad, relu);
+    } else {
+        dim3 grid((Wout + CV_TW - 1) / CV_TW, (Hout + CV_TH - 1) / CV_TH, B * ((Cout + 15) / 16));
+        hipLaunchKernelGGL((conv5_kernel<AI, AO, 16>), grid, block, 0, s, in, w, bias, out, Cin, Hin, Win, Cout, Hout,
+                           Wout, pad, relu);
+    }
     return hipGetLastError();
 }
 

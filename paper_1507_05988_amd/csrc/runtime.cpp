@@ -35,7 +35,6 @@ constexpr double kMe = 9.1093837015e-31;
 constexpr double kQe = 1.602176634e-19;
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kRowElems = 8;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -333,7 +332,7 @@ fcn_status build_plan(fcn_plan_t p) {
         b.scan = 0;
         for (int i : kv.second)
             if (p->dinst[i].need_rho != 0.0) b.scan = RK_SCAN;
-        const int rpw = row_rows_per_group(b.nt, kRowElems);
+        const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt));
         b.grid = (b.nitems + rpw - 1) / rpw;
         p->row_buckets.push_back(b);
     }
@@ -444,7 +443,7 @@ hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, in
         a.seed_slots = seed;
         a.stage_len = stage_len;
         const bool nl = (flags & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
-        hipError_t e = launch_row(p->precision, b.nt, kRowElems, nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
+        hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt), nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
                                   bi == 0 ? e0 : nullptr, bi + 1 == nb ? e1 : nullptr);
         if (e != hipSuccess) return e;
     }
@@ -660,7 +659,11 @@ fcn_status fcn_plan_tiles(fcn_plan_t p, int32_t *col_tile, int32_t *col_rows, in
     if (!p) return FCN_E_ARG;
     if (col_tile) *col_tile = p->col_w;
     if (col_rows) *col_rows = p->col_l;
-    if (row_elems) *row_elems = kRowElems;
+    if (row_elems) {
+        int nt_max = 0;
+        for (const auto &in : p->insts) nt_max = std::max(nt_max, (int)in.nt);
+        *row_elems = row_elems_for(nt_max);
+    }
     return FCN_OK;
 }
 

@@ -175,6 +175,12 @@ def config_parareal_trajectory(j: int, nr=512, nt=2048) -> dict:
 
 PARAREAL_WINDOWS = 32
 PARAREAL_STEPS_PER_WINDOW = 50
+# Learned-coarse variant of the same trajectories: 8 windows of 250 steps (5 cm, 0.4 m in
+# all).  Over 1 cm windows the classical coarse step is within 5e-8..3e-7 of the fine steps
+# (FP64), below FP32 field resolution, so a learned correction has nothing to learn there;
+# over 5 cm its error is 1e-6..1e-3 per window.
+LEARNED_WINDOWS = 8
+LEARNED_STEPS_PER_WINDOW = 250
 
 
 def random_field(nr: int, nt: int, seed: int, scale: float = 1.0, dtype=np.complex128) -> np.ndarray:

@@ -160,7 +160,7 @@ def test_train_coarse_on_fcn_trajectories():
     the loss falls."""
     net = coarse.CoarseNet(channels=8, bf16=True, max_batch=16, max_h=32, max_w=64, training=True, seed=1)
     hist = coarse.train_coarse(net, range(8), kappa=1e-5, batch_traj=8, crops_per_traj=2, crop_h=32, crop_w=64,
-                               lr=3e-3, windows=24, steps_per_window=10, seed=0,
+                               lr=3e-3, windows=24, steps_per_window=10, seed=0, updates_per_window=1, warmup=1,
                                make_inst=lambda j: wl.config_parareal_trajectory(j, nr=128, nt=512))
     say(f"  loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     assert len(hist) == 24 and np.all(np.isfinite(hist))

@@ -103,6 +103,60 @@ def cpu_baseline(inst, a0, seconds: float):
                       f"(after 1 warm step), {dt:.1f} s"}
 
 
+def coarse_net_measurement(torch):
+    """The learned coarse network (C = 32): full-grid forward on one 512 x 2048 window (the
+    inference of one coarse step; 4.4e11 flop counting a complex multiply-add as 4 real ones)
+    and training steps (forward, loss, backward, Adam) on 64 crops of 128 x 128, for BF16 and
+    FP32 activations; device time by events on the network's stream."""
+    from paper_1507_05988_amd import coarse
+    from paper_1507_05988_amd import workloads as wl
+
+    inst = wl.config_parareal_trajectory(2000)
+    nr, nt = int(inst["nr"]), int(inst["nt"])
+    field = torch.from_numpy(wl.gaussian_field(inst, np.complex64).reshape(-1)).cuda()
+    flops = 2.0 * 25 * 2 * 64 * (nr + 12) * (nt + 12) + 2.0 * 25 * 64 * 64 * ((nr + 8) * (nt + 8) + (nr + 4) * (nt + 4)) \
+        + 2.0 * 25 * 64 * 2 * nr * nt
+    out = {"flop_per_forward": flops, "peak_tflops_fp32_vector": 157.3}
+
+    def timed(fn, reps, stream):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    for bf16 in (True, False):
+        key = "bf16" if bf16 else "fp32"
+        net = coarse.CoarseNet(channels=32, bf16=bf16, max_batch=1, max_h=nr, max_w=nt)
+        smp = coarse.samples_tensor(torch, net.device, [(0, 0, 0, 0, 1.0 / coarse.S_REF, 1.0)])
+        net.input(field, smp, 1, nr, nt, nr, nt)
+        ms = timed(lambda: net.forward(1, nr, nt), 5, net.stream)
+        net.close()
+        tr = coarse.CoarseNet(channels=32, bf16=bf16, max_batch=64, max_h=128, max_w=128, training=True)
+        smp = coarse.samples_tensor(torch, tr.device, [(0, 0, (7 * i) % 256, nt // 2 - 64 + i, 1.0 / coarse.S_REF, 1.0)
+                                                       for i in range(64)])
+        tgt = torch.ones((64, 2, 128, 128), dtype=torch.float32, device=tr.device)
+        tr.input(field, smp, 64, nr, nt, 128, 128)
+        row0 = [(7 * i) % 256 for i in range(64)]
+
+        def step():
+            tr.forward(64, 128, 128)
+            tr.loss(tgt, row0, 64, 128, 128)
+            tr.backward(64, 128, 128)
+            tr.adam(1e-4)
+
+        ms_tr = timed(step, 3, tr.stream)
+        tr.close()
+        out[key] = {"forward_ms": round(ms, 4), "inferences_per_s": round(1e3 / ms, 2),
+                    "tflops": round(flops / ms * 1e-9, 2), "frac_fp32_vector_peak": round(flops / ms * 1e-9 / 157.3, 4),
+                    "train_step_ms": round(ms_tr, 3), "train_samples_per_s": round(64 * 1e3 / ms_tr, 1)}
+    return out
+
+
 def parareal_measurement(torch):
     """Parareal along z for held-out learned-coarse trajectory 2000 (Nr=512, Nt=2048, Kerr only,
     never used in training), fine and coarse FCN steps in FP32 storage, against the serial
@@ -176,6 +230,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
+    ap.add_argument("--no-net", action="store_true")
+    ap.add_argument("--only-net", action="store_true",
+                    help="only the learned coarse network's inference and training rates (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 10 times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -192,6 +249,10 @@ def main():
     import torch
     from paper_1507_05988_amd import fcn
     from paper_1507_05988_amd import workloads as wl
+
+    if args.only_net:
+        print(json.dumps({"coarse_net": coarse_net_measurement(torch)}), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.ones(64 * 2 ** 20, dtype=torch.complex64, device="cuda")
@@ -335,6 +396,8 @@ def main():
 
     if not args.no_parareal:
         out["parareal"] = parareal_measurement(torch)
+    if not args.no_net:
+        out["coarse_net"] = coarse_net_measurement(torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a0, args.cpu_seconds)

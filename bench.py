@@ -107,7 +107,10 @@ def coarse_net_measurement(torch):
     """The learned coarse network (C = 32): full-grid forward on one 512 x 2048 window (the
     inference of one coarse step; 4.4e11 flop counting a complex multiply-add as 4 real ones)
     and training steps (forward, loss, backward, Adam) on 64 crops of 128 x 128, for BF16 and
-    FP32 activations; device time by events on the network's stream."""
+    FP32 activations (BF16 with the hidden layers on BF16 matrix cores, and on FP32 vector
+    FMAs); device time by events on the network's stream.  Flop rates are against the FP32
+    vector peak (157.3 TFLOP/s) and, for the matrix-core form, the dense BF16 peak
+    (2.5 PFLOP/s)."""
     from paper_1507_05988_amd import coarse
     from paper_1507_05988_amd import workloads as wl
 
@@ -116,7 +119,7 @@ def coarse_net_measurement(torch):
     field = torch.from_numpy(wl.gaussian_field(inst, np.complex64).reshape(-1)).cuda()
     flops = 2.0 * 25 * 2 * 64 * (nr + 12) * (nt + 12) + 2.0 * 25 * 64 * 64 * ((nr + 8) * (nt + 8) + (nr + 4) * (nt + 4)) \
         + 2.0 * 25 * 64 * 2 * nr * nt
-    out = {"flop_per_forward": flops, "peak_tflops_fp32_vector": 157.3}
+    out = {"flop_per_forward": flops}
 
     def timed(fn, reps, stream):
         fn()
@@ -129,14 +132,13 @@ def coarse_net_measurement(torch):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    for bf16 in (True, False):
-        key = "bf16" if bf16 else "fp32"
-        net = coarse.CoarseNet(channels=32, bf16=bf16, max_batch=1, max_h=nr, max_w=nt)
+    for key, bf16, mfma in (("bf16_mfma", True, True), ("bf16", True, False), ("fp32", False, False)):
+        net = coarse.CoarseNet(channels=32, bf16=bf16, max_batch=1, max_h=nr, max_w=nt, mfma=mfma)
         smp = coarse.samples_tensor(torch, net.device, [(0, 0, 0, 0, 1.0 / coarse.S_REF, 1.0)])
         net.input(field, smp, 1, nr, nt, nr, nt)
         ms = timed(lambda: net.forward(1, nr, nt), 5, net.stream)
         net.close()
-        tr = coarse.CoarseNet(channels=32, bf16=bf16, max_batch=64, max_h=128, max_w=128, training=True)
+        tr = coarse.CoarseNet(channels=32, bf16=bf16, max_batch=64, max_h=128, max_w=128, training=True, mfma=mfma)
         smp = coarse.samples_tensor(torch, tr.device, [(0, 0, (7 * i) % 256, nt // 2 - 64 + i, 1.0 / coarse.S_REF, 1.0)
                                                        for i in range(64)])
         tgt = torch.ones((64, 2, 128, 128), dtype=torch.float32, device=tr.device)
@@ -151,8 +153,10 @@ def coarse_net_measurement(torch):
 
         ms_tr = timed(step, 3, tr.stream)
         tr.close()
+        peak = 2500.0 if mfma else 157.3
         out[key] = {"forward_ms": round(ms, 4), "inferences_per_s": round(1e3 / ms, 2),
-                    "tflops": round(flops / ms * 1e-9, 2), "frac_fp32_vector_peak": round(flops / ms * 1e-9 / 157.3, 4),
+                    "roofline": {"bound": "mfma" if mfma else "alu", "achieved": round(flops / ms * 1e-9, 2),
+                                 "peak": peak, "unit": "TFLOP/s", "frac": round(flops / ms * 1e-9 / peak, 4)},
                     "train_step_ms": round(ms_tr, 3), "train_samples_per_s": round(64 * 1e3 / ms_tr, 1)}
     return out
 

@@ -189,7 +189,10 @@ fcn_status fcn_plan_tiles(fcn_plan_t plan, int32_t *col_tile, int32_t *col_rows,
  * scale out_scale = kappa s per sample, the network predicts (F - C) / (kappa s)).  Parameters: caller-owned FP32 buffer
  * of fcn_net_param_count floats, per layer W[co][ci][5][5] as (re, im) pairs then b[co] as
  * (re, im); gradients have the same layout and are the pairs (dL/dRe w, dL/dIm w).
- * Activations are stored in BF16 (act_bf16 = 1) or FP32 and accumulated in FP32.
+ * Activations are stored in BF16 (act_bf16 = 1 or 2) or FP32 (act_bf16 = 0) and accumulated
+ * in FP32.  With act_bf16 = 1 the hidden 32 -> 32 complex layers (64 -> 64 real channels) run
+ * as BF16 matrix-core products (weights rounded to BF16); act_bf16 = 2 keeps them on FP32
+ * vector FMAs with FP32 weights.
  * All network calls are asynchronous on the bound stream except fcn_net_loss. */
 typedef struct fcn_net_s *fcn_net_t;
 

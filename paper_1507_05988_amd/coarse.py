@@ -55,7 +55,7 @@ def samples_tensor(torch, device, rows):
 
 class CoarseNet:
     def __init__(self, channels=32, bf16=True, max_batch=1, max_h=64, max_w=64, training=False, params=None,
-                 seed=0, device=0, stream=None):
+                 seed=0, device=0, stream=None, mfma=True):
         import torch
 
         self.torch = torch
@@ -64,7 +64,8 @@ class CoarseNet:
         self.bf16 = bool(bf16)
         self.device = torch.device("cuda", device)
         self._h = ctypes.c_void_p()
-        self._check(self.lib.fcn_net_create(channels, int(bf16), ctypes.byref(self._h)))
+        act = (1 if mfma else 2) if bf16 else 0
+        self._check(self.lib.fcn_net_create(channels, act, ctypes.byref(self._h)))
         n = ctypes.c_size_t()
         self._check(self.lib.fcn_net_param_count(self._h, ctypes.byref(n)))
         self.nparams = n.value

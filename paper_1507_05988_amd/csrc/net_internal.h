@@ -26,6 +26,14 @@ struct NetSample {
 hipError_t launch_conv5(int act_bf16, int in_kind, int out_kind, const void *in, const float *w, const float *bias,
                         void *out, int B, int Cin, int Hin, int Win, int Cout, int Hout, int Wout, int pad, int relu,
                         hipStream_t s);
+// BF16 MFMA convolution of the Cin -> 64 real-channel layers (Cin = 32 or 64), valid, BF16 in
+// and out; its weights are packed from the real-form FP32 weights by launch_pack_mfma_weights
+// into conv5_mfma_weight_bytes(Cin) bytes.
+bool conv5_mfma_supported(int Cin, int Cout);
+size_t conv5_mfma_weight_bytes(int Cin);
+hipError_t launch_pack_mfma_weights(const float *wr, void *wA, int Cin, hipStream_t s);
+hipError_t launch_conv5_mfma(const void *in, const void *wA, const float *bias, void *out, int B, int Cin, int Hin,
+                             int Win, int Hout, int Wout, int relu, hipStream_t s);
 hipError_t launch_conv5_wgrad(int act_bf16, const void *in, const float *g, float *gw, float *gb, int B, int Cin,
                               int Hin, int Win, int Cout, int Hout, int Wout, hipStream_t s);
 hipError_t launch_relu_mask(int act_bf16, float *g, const void *act, size_t n, hipStream_t s);

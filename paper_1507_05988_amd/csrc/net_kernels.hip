@@ -122,6 +122,120 @@ __global__ void __launch_bounds__(256) conv5_kernel(const AI *__restrict__ in, c
     }
 }
 
+// ---------------------------------------------------------------- BF16 MFMA convolution
+
+// The 64 -> 64 real-channel layers as an implicit GEMM on the matrix cores:
+// out[co][p] = sum_{tap, ci} W[co][ci][tap] in[ci][p + tap], one v_mfma_f32_16x16x32_bf16 per
+// (16 output channels) x (16 pixels) x (32 input channels of one tap).  Operand layout of
+// that instruction (lane l of the wave): A[m = l % 16][k = 8 (l / 16) + i], B[k = 8 (l / 16) + i]
+// [n = l % 16], i < 8; result C[m = 4 (l / 16) + i][n = l % 16], i < 4.  A = weights (m: output
+// channel), B = inputs (n: pixel), so a lane's B operand is 8 consecutive input channels of
+// one pixel: the input tile is staged in LDS channel-innermost ([y][x][c], 72 BF16 per pixel,
+// 8 of them padding that spreads the 16-byte reads over the banks).  A fragments are packed
+// once per weight update in exactly the lane order (pack_mfma_weights_kernel) and read with
+// one 16-byte load per lane.
+// Workgroup: 4 x 64 outputs, 4 waves; wave w computes output row w, 4 pixel tiles x 4 channel
+// tiles (16 accumulators of 4 floats).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int MF_TH = 4, MF_TW = 64, MF_COUT = 64;
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// wA[((t * KC + kc) * 4 + ct) * 64 + lane] = W[16 ct + lane % 16][32 kc + 8 (lane / 16) + i][t], i < 8
+__global__ void pack_mfma_weights_kernel(const float *__restrict__ wr, uint4 *__restrict__ wA, int cin, int kc_n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 25 * kc_n * 4 * 64) return;
+    const int lane = idx & 63, ct = (idx >> 6) & 3, tk = idx >> 8;
+    const int kc = tk % kc_n, t = tk / kc_n;
+    const int co = 16 * ct + (lane & 15), ci0 = 32 * kc + 8 * (lane >> 4);
+    uint16_t h[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) h[i] = bf16_rne(wr[((size_t)co * cin + ci0 + i) * 25 + t]);
+    uint4 v;
+    v.x = h[0] | ((uint32_t)h[1] << 16);
+    v.y = h[2] | ((uint32_t)h[3] << 16);
+    v.z = h[4] | ((uint32_t)h[5] << 16);
+    v.w = h[6] | ((uint32_t)h[7] << 16);
+    wA[idx] = v;
+}
+
+// Valid 5x5 convolution, BF16 in and out, Cin = 32 KC, Cout = 64; grid (ceil(Wout/64),
+// ceil(Hout/4), B), 256 threads.
+template <int KC>
+__global__ void __launch_bounds__(256) conv5_mfma_kernel(const bf16_t *__restrict__ in, const uint4 *__restrict__ wA,
+                                                         const float *__restrict__ bias, bf16_t *__restrict__ out,
+                                                         int Hin, int Win, int Hout, int Wout, int relu) {
+    constexpr int CIN = 32 * KC;
+    constexpr int PIXS = CIN + 8;           // BF16 per staged pixel
+    constexpr int SW = MF_TW + 4, SH = MF_TH + 4;
+    __shared__ __align__(16) uint16_t s_in[SH * SW * PIXS];
+    const int b = blockIdx.z;
+    const int y0 = blockIdx.y * MF_TH, x0 = blockIdx.x * MF_TW;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+    for (int idx = tid; idx < CIN * SH * SW; idx += 256) {
+        const int c = idx / (SH * SW), rem = idx % (SH * SW);
+        const int yy = rem / SW, xx = rem % SW;
+        const int gy = y0 + yy, gx = x0 + xx;
+        uint16_t v = 0;
+        if (gy < Hin && gx < Win) v = in[(((size_t)b * CIN + c) * Hin + gy) * Win + gx].v;
+        s_in[(yy * SW + xx) * PIXS + c] = v;
+    }
+    __syncthreads();
+
+    f32x4_t acc[4][4];
+#pragma unroll
+    for (int pt = 0; pt < 4; pt++)
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++) acc[pt][ct] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    const int n = lane & 15, kg = lane >> 4;
+    for (int t = 0; t < 25; t++) {
+        const int ky = t / 5, kx = t % 5;
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++) {
+            bf16x8_t a[4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ct++) {
+                const uint4 w = wA[((t * KC + kc) * 4 + ct) * 64 + lane];
+                a[ct] = __builtin_bit_cast(bf16x8_t, w);
+            }
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++) {
+                const uint4 xv = *reinterpret_cast<const uint4 *>(
+                    &s_in[((wave + ky) * SW + 16 * pt + n + kx) * PIXS + 32 * kc + 8 * kg]);
+                const bf16x8_t bx = __builtin_bit_cast(bf16x8_t, xv);
+#pragma unroll
+                for (int ct = 0; ct < 4; ct++) acc[pt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ct], bx, acc[pt][ct], 0, 0, 0);
+            }
+        }
+    }
+
+    const int y = y0 + wave;
+    if (y < Hout) {
+#pragma unroll
+        for (int pt = 0; pt < 4; pt++) {
+            const int x = x0 + 16 * pt + n;
+            if (x < Wout) {
+#pragma unroll
+                for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        const int co = 16 * ct + 4 * kg + i;
+                        float v = acc[pt][ct][i] + bias[co];
+                        if (relu) v = fmaxf(v, 0.0f);
+                        out[(((size_t)b * MF_COUT + co) * Hout + y) * Wout + x].v = bf16_rne(v);
+                    }
+            }
+        }
+    }
+}
+
 // gw[co][ci][ky][kx] = sum_{b,y<Hout,x<Wout} in[b][ci][y+ky][x+kx] g[b][co][y][x]
 // gb[co] = sum g[b][co][y][x] (written by the ci = 0 block).  One workgroup per (co, ci)
 // and a fixed reduction tree: deterministic.
@@ -410,6 +524,31 @@ hipError_t launch_conv5(int act_bf16, int in_kind, int out_kind, const void *in,
             return conv5_t((const float *)in, w, bias, (bf16_t *)out, B, Cin, Hin, Win, Cout, Hout, Wout, pad, relu, s);
     }
     return conv5_t((const float *)in, w, bias, (float *)out, B, Cin, Hin, Win, Cout, Hout, Wout, pad, relu, s);
+}
+
+bool conv5_mfma_supported(int Cin, int Cout) { return Cout == MF_COUT && (Cin == 32 || Cin == 64); }
+
+size_t conv5_mfma_weight_bytes(int Cin) { return (size_t)25 * (Cin / 32) * 4 * 64 * sizeof(uint4); }
+
+hipError_t launch_pack_mfma_weights(const float *wr, void *wA, int Cin, hipStream_t s) {
+    const int n = 25 * (Cin / 32) * 4 * 64;
+    hipLaunchKernelGGL(pack_mfma_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, wr, (uint4 *)wA, Cin, Cin / 32);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv5_mfma(const void *in, const void *wA, const float *bias, void *out, int B, int Cin, int Hin,
+                             int Win, int Hout, int Wout, int relu, hipStream_t s) {
+    if (Hout != Hin - 4 || Wout != Win - 4) return hipErrorInvalidValue;
+    const dim3 grid((Wout + MF_TW - 1) / MF_TW, (Hout + MF_TH - 1) / MF_TH, B);
+    if (Cin == 64)
+        hipLaunchKernelGGL(conv5_mfma_kernel<2>, grid, dim3(256), 0, s, (const bf16_t *)in, (const uint4 *)wA, bias,
+                           (bf16_t *)out, Hin, Win, Hout, Wout, relu);
+    else if (Cin == 32)
+        hipLaunchKernelGGL(conv5_mfma_kernel<1>, grid, dim3(256), 0, s, (const bf16_t *)in, (const uint4 *)wA, bias,
+                           (bf16_t *)out, Hin, Win, Hout, Wout, relu);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_conv5_wgrad(int act_bf16, const void *in, const float *g, float *gw, float *gb, int B, int Cin,

@@ -25,6 +25,7 @@ size_t al(size_t x) { return (x + 255) / 256 * 256; }
 struct fcn_net_s {
     int C = 32;
     int act_bf16 = 1;
+    int mfma = 1;             // BF16 layers 64 -> 64 real channels on the matrix cores
     int cin[4], cout[4];      // complex channels per layer
     size_t poff[5];           // float offsets of the layers' parameters; poff[4] = total
     // bound state
@@ -37,6 +38,7 @@ struct fcn_net_s {
     int64_t adam_t = 0;
     // workspace pieces
     float *wr[4], *br[4], *wt[4], *gwr[4], *gbr[4];
+    void *wA[4];              // packed MFMA weight fragments (layers that use the matrix cores)
     void *act[4];             // act[0]: input; act[1..3]: post-activations of layers 1..3
     float *out = nullptr;     // FP32 [b][2][h][w]
     float *g[2];              // FP32 gradient ping-pong
@@ -46,6 +48,7 @@ struct fcn_net_s {
     std::string err;
 
     size_t act_bytes() const { return act_bf16 ? 2 : 4; }
+    bool use_mfma(int l) const { return act_bf16 && mfma && l < 3 && conv5_mfma_supported(2 * cin[l], 2 * cout[l]); }
 };
 
 namespace {
@@ -73,6 +76,7 @@ size_t layout(fcn_net_t n, int B, int H, int W, int training, unsigned char *p) 
         n->wt[l] = (float *)take(nw * 4);
         n->gwr[l] = (float *)take(training ? nw * 4 : 0);
         n->gbr[l] = (float *)take(training ? (size_t)2 * n->cout[l] * 4 : 0);
+        n->wA[l] = n->use_mfma(l) ? take(conv5_mfma_weight_bytes(2 * n->cin[l])) : nullptr;
     }
     const size_t ab = n->act_bytes();
     const size_t C2 = 2 * (size_t)n->C;
@@ -103,6 +107,7 @@ hipError_t expand_all(fcn_net_t n) {
     hipError_t e = hipSuccess;
     for (int l = 0; l < 4 && e == hipSuccess; l++) {
         e = launch_expand_weights(n->params + n->poff[l], n->wr[l], n->br[l], n->cout[l], n->cin[l], n->stream);
+        if (e == hipSuccess && n->use_mfma(l)) e = launch_pack_mfma_weights(n->wr[l], n->wA[l], 2 * n->cin[l], n->stream);
         if (e == hipSuccess && n->training)
             e = launch_flip_transpose(n->wr[l], n->wt[l], 2 * n->cout[l], 2 * n->cin[l], n->stream);
     }
@@ -123,10 +128,11 @@ extern "C" {
 fcn_status fcn_net_create(int32_t channels, int32_t act_bf16, fcn_net_t *out) {
     if (!out) return FCN_E_ARG;
     *out = nullptr;
-    if (channels < 1 || channels > 64) return FCN_E_ARG;
+    if (channels < 1 || channels > 64 || act_bf16 < 0 || act_bf16 > 2) return FCN_E_ARG;
     fcn_net_t n = new fcn_net_s();
     n->C = channels;
     n->act_bf16 = act_bf16 ? 1 : 0;
+    n->mfma = act_bf16 == 1 ? 1 : 0;
     const int ci[4] = {1, channels, channels, channels}, co[4] = {channels, channels, channels, 1};
     size_t o = 0;
     for (int l = 0; l < 4; l++) {
@@ -212,8 +218,11 @@ fcn_status fcn_net_forward(fcn_net_t n, int32_t batch, int32_t h, int32_t w, flo
         const int Hi = lin_h(l, h), Wi = lin_h(l, w), Ho = Hi - 4, Wo = Wi - 4;
         const void *src = n->act[l];
         void *dst = (l < 3) ? n->act[l + 1] : (void *)n->out;
-        e = launch_conv5(n->act_bf16, 1, l < 3 ? 1 : 0, src, n->wr[l], n->br[l], dst, batch, 2 * n->cin[l], Hi, Wi,
-                         2 * n->cout[l], Ho, Wo, 0, l < 3 ? 1 : 0, n->stream);
+        if (n->use_mfma(l))
+            e = launch_conv5_mfma(src, n->wA[l], n->br[l], dst, batch, 2 * n->cin[l], Hi, Wi, Ho, Wo, 1, n->stream);
+        else
+            e = launch_conv5(n->act_bf16, 1, l < 3 ? 1 : 0, src, n->wr[l], n->br[l], dst, batch, 2 * n->cin[l], Hi, Wi,
+                             2 * n->cout[l], Ho, Wo, 0, l < 3 ? 1 : 0, n->stream);
     }
     if (e == hipSuccess && out)
         e = hipMemcpyAsync(out, n->out, (size_t)batch * 2 * h * w * 4, hipMemcpyDeviceToDevice, n->stream);

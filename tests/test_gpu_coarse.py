@@ -236,3 +236,37 @@ def test_parareal_with_network_runs():
                               kappa=1e-6, fallback=False)
     assert all(torch.isfinite(u).all() for u in U)
     assert hist[1]["change"] < 1e-3
+
+
+@pytest.mark.parametrize("H,W", [(12, 20), (40, 150)])
+def test_mfma_layers_match_reference_and_vector_path(H, W):
+    """C = 32 with BF16 activations: the hidden layers run as BF16 matrix-core products (ragged
+    4 x 64 tiles here).  Against the FP64 reference: BF16 bound 1e-2; against the same network
+    on FP32 vector FMAs with BF16 activations: within the BF16 rounding of the weights."""
+    import torch
+    C, B = 32, 2
+    rng = np.random.default_rng(21)
+    nr, nt = 60, 200
+    field = (rng.standard_normal((nr, nt)) + 1j * rng.standard_normal((nr, nt))).astype(np.complex64)
+    field[-1] = 0
+    p = coarse.init_params(C, seed=5)
+    p[-2:] = 0.0
+    outs = {}
+    for mfma in (True, False):
+        net = coarse.CoarseNet(channels=C, bf16=True, max_batch=B, max_h=H, max_w=W, params=p, mfma=mfma)
+        spec = [(0, 0, 0, 7, 1.0, 1.0), (0, 0, 13, nt - 30, 1.0, 1.0)]
+        smp = coarse.samples_tensor(torch, net.device, spec)
+        net.input(torch.from_numpy(field.reshape(-1)).to(net.device), smp, B, nr, nt, H, W)
+        out = torch.zeros((B, 2, H, W), dtype=torch.float32, device=net.device)
+        net.forward(B, H, W, out)
+        o = out.cpu().numpy()
+        outs[mfma] = o[:, 0] + 1j * o[:, 1]
+        net.close()
+    x = np.stack([_window(field.astype(np.complex128), r0, c0, H, W, s)[None] for (_, _, r0, c0, s, _) in spec])
+    ref, _ = convnet.forward(convnet.unflat(p.astype(np.float64), C), x)
+    ref = ref[:, 0]
+    e_m = np.linalg.norm(outs[True] - ref) / np.linalg.norm(ref)
+    e_v = np.linalg.norm(outs[False] - ref) / np.linalg.norm(ref)
+    e_mv = np.linalg.norm(outs[True] - outs[False]) / np.linalg.norm(ref)
+    say(f"  {H}x{W}: MFMA vs FP64 {e_m:.2e}, vector vs FP64 {e_v:.2e}, MFMA vs vector {e_mv:.2e}")
+    assert e_m < 1e-2 and e_v < 1e-2 and e_mv < 1e-2

@@ -272,7 +272,13 @@ def main():
     a0 = wl.gaussian_field(inst)
 
     # ---- FP32 timed region
-    p32 = fcn.Plan(inst, precision="fp32")
+    from paper_1507_05988_amd import autotune
+
+    tiles = {prec: autotune.tune(inst, prec, steps=50, repeats=3) for prec in ("fp32", "fp64", "fp32_storage")}
+    tile_kw = {prec: dict(col_tile=t["col_tile"], col_rows=t["col_rows"]) for prec, t in tiles.items()}
+    print("[bench] column tiles (autotuned): " + ", ".join(f"{k} {t['col_tile']}x{t['col_rows']}" for k, t in tiles.items()),
+          file=sys.stderr, flush=True)
+    p32 = fcn.Plan(inst, precision="fp32", **tile_kw["fp32"])
     init32 = p32.pack(a0.astype(np.complex64))
     f32 = init32.clone()
     if args.warmup > 0:
@@ -318,11 +324,13 @@ def main():
                    "terms": "diffraction+GVD+Kerr(n2,n4)+plasma+MPA(K=8)+collisions"},
         "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1),
         "roofline": roofline,
+        "column_tiles": {k: {"col_tile": t["col_tile"], "col_rows": t["col_rows"],
+                             "col_us": {kk: round(v * 1e3, 2) for kk, v in t["table"].items()}} for k, t in tiles.items()},
     }
 
     # ---- FP64 plain method on the same workload
     if not args.no_fp64:
-        p64 = fcn.Plan(inst, precision="fp64")
+        p64 = fcn.Plan(inst, precision="fp64", **tile_kw["fp64"])
         init64 = p64.pack(a0)
         f64 = init64.clone()
         p64.step(f64, min(args.warmup, 50) or 1)
@@ -335,7 +343,7 @@ def main():
                              "steps": n64, "row_ms": round(r64, 6), "col_ms": round(c64, 6),
                              "hbm_gbs_algorithmic": round(pts * n64 / s64 * 64 / 1e9, 1)}
         del p64, f64
-        pm = fcn.Plan(inst, precision="fp32_storage")
+        pm = fcn.Plan(inst, precision="fp32_storage", **tile_kw["fp32_storage"])
         initm = pm.pack(a0.astype(np.complex64))
         fm = initm.clone()
         pm.step(fm, min(args.warmup, 50) or 1)

@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 // kernel's own start and end (timing without the gaps between launches).
 template <typename R, typename ST, int NT, int FLAGS>
 static hipError_t launch_row_t(const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    constexpr int E = row_elems_for(NT);
+    constexpr int E = row_elems_for(NT, sizeof(R) == 8);
     using Cfg = RowCfg<R, NT, E, FLAGS>;
     hipExtLaunchKernelGGL((row_kernel<R, ST, NT, E, FLAGS>), dim3(grid), dim3(Cfg::THREADS), 0, s, e0, e1, 0, a);
     return hipGetLastError();
@@ -565,7 +565,7 @@ int row_rows_per_group(int nt, int elems) {
 
 hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1) {
-    if (elems != row_elems_for(nt)) return hipErrorInvalidValue;
+    if (elems != row_elems_for(nt, precision != 1)) return hipErrorInvalidValue;
     switch (precision) {
         case 0: return launch_row_p<double, double>(nt, flags, a, grid, s, e0, e1);
         case 1: return launch_row_p<float, float>(nt, flags, a, grid, s, e0, e1);

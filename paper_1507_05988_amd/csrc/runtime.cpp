@@ -332,7 +332,7 @@ fcn_status build_plan(fcn_plan_t p) {
         b.scan = 0;
         for (int i : kv.second)
             if (p->dinst[i].need_rho != 0.0) b.scan = RK_SCAN;
-        const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt));
+        const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt, p->precision != FCN_FP32));
         b.grid = (b.nitems + rpw - 1) / rpw;
         p->row_buckets.push_back(b);
     }
@@ -443,7 +443,7 @@ hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, in
         a.seed_slots = seed;
         a.stage_len = stage_len;
         const bool nl = (flags & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
-        hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt), nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
+        hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt, p->precision != FCN_FP32), nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
                                   bi == 0 ? e0 : nullptr, bi + 1 == nb ? e1 : nullptr);
         if (e != hipSuccess) return e;
     }
@@ -662,7 +662,7 @@ fcn_status fcn_plan_tiles(fcn_plan_t p, int32_t *col_tile, int32_t *col_rows, in
     if (row_elems) {
         int nt_max = 0;
         for (const auto &in : p->insts) nt_max = std::max(nt_max, (int)in.nt);
-        *row_elems = row_elems_for(nt_max);
+        *row_elems = row_elems_for(nt_max, p->precision != FCN_FP32);
     }
     return FCN_OK;
 }

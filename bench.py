@@ -103,6 +103,36 @@ def cpu_baseline(inst, a0, seconds: float):
                       f"(after 1 warm step), {dt:.1f} s"}
 
 
+def batched_sweep_measurement(torch):
+    """The 64-pulse ragged sweep (Nr in {256, 512, 1024}, Nt in {512 ... 4096}, about 7.5e7
+    points, Kerr, one FP32 plan with autotuned column tiles), 100 steps: aggregate throughput
+    and per-pass kernel times (kernel-own events; one launch per distinct Nt or Nr)."""
+    from paper_1507_05988_amd import autotune, fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    insts = wl.config_batch()
+    pts = sum(int(i["nr"]) * int(i["nt"]) for i in insts)
+    t = autotune.tune(insts, "fp32", steps=10, repeats=2)
+    plan = fcn.Plan(insts, precision="fp32", col_tile=t["col_tile"], col_rows=t["col_rows"])
+    init = plan.pack([wl.gaussian_field(i, np.complex64) for i in insts])
+    f = init.clone()
+    plan.step(f, 5)
+    sec = timed_steps(plan, f, init, wl.BATCH_STEPS, torch)
+    f.copy_(init)
+    krow, kcol, _ = plan.step_timed(f, 20)
+    plan.sync()
+    value = pts * wl.BATCH_STEPS / sec
+    byt = pts * 16
+    return {"points": pts, "instances": len(insts), "steps": wl.BATCH_STEPS, "value": round(value, 1),
+            "unit": "grid-pt z-steps/s", "ms_per_step": round(sec * 1e3 / wl.BATCH_STEPS, 4),
+            "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1), "row_pass_ms": round(krow, 4),
+            "col_pass_ms": round(kcol, 4), "col_tile": [t["col_tile"], t["col_rows"]],
+            "roofline_row_pass": {"bound": "hbm", "achieved": round(byt / (krow * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(byt / (krow * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "roofline_col_pass": {"bound": "hbm", "achieved": round(byt / (kcol * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(byt / (kcol * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
 def coarse_net_measurement(torch):
     """The learned coarse network (C = 32): full-grid forward on one 512 x 2048 window (the
     inference of one coarse step; 4.4e11 flop counting a complex multiply-add as 4 real ones)
@@ -235,6 +265,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--no-net", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only-net", action="store_true",
                     help="only the learned coarse network's inference and training rates (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -406,6 +437,8 @@ def main():
                 break
         out["accuracy_fp32_vs_fp64"] = acc
 
+    if not args.no_batch:
+        out["batched_sweep"] = batched_sweep_measurement(torch)
     if not args.no_parareal:
         out["parareal"] = parareal_measurement(torch)
     if not args.no_net:

@@ -128,12 +128,13 @@ hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs
 hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int row_rows_per_group(int nt, int elems);
-// Elements per thread of the row kernel.  At nt = 8192 always 16: a row stays within 512
-// threads and so within the 256-VGPR budget (1024 threads would cap every thread at 128
-// VGPRs and spill).  Below, FP32 arithmetic uses 8 (radix-8 passes); FP64 arithmetic uses 16
-// from nt = 2048 (three radix-16 passes instead of four radix-8 ones: 40.5 against 44.2 us
-// for the full-model row pass, while FP32 is slower with 16, 25.8 against 19.4 us).
-constexpr int row_elems_for(int nt, bool fp64_arith) { return nt >= 8192 || (fp64_arith && nt >= 2048) ? 16 : 8; }
+// Elements per thread of the row kernel.  16 from nt = 4096: at nt = 8192 a row stays within
+// 512 threads and so within the 256-VGPR budget (1024 threads would cap every thread at 128
+// VGPRs and spill); at nt = 4096 a 256-thread row lets two rows share a CU where a 512-thread
+// one at 163 VGPRs fits alone (436 against 531 us for the 4096-point rows of the batched
+// sweep).  With FP64 arithmetic also 16 at nt = 2048 (three radix-16 passes: 39.5 against
+// 44.2 us for the full-model row pass); FP32 keeps 8 there (25.8 against 19.4 us with 16).
+constexpr int row_elems_for(int nt, bool fp64_arith) { return nt >= 4096 || (fp64_arith && nt >= 2048) ? 16 : 8; }
 hipError_t launch_finalize(const DevInst *inst, int batch, const double *row_diag, const double *zpos,
                            const double *dz_ring, const DevState *state, double *out, hipStream_t s);
 hipError_t launch_init_state(DevState *state, unsigned long long *phi_slot, double *dz_ring, double *zpos,

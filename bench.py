@@ -200,8 +200,10 @@ def parareal_measurement(torch):
       * the learned-coarse variant, 8 windows x 250 steps, classical and learned coarse step
         (the shipped network is trained for these 5 cm windows).
     Errors: r-weighted relative field error against the FP64 solution, max over windows, per
-    iteration (k = 0 is the coarse sweep alone); stopping rule: change < 1e-4, or the
-    corrections grow.  Wall time includes the host-side convergence checks."""
+    iteration (k = 0 is the coarse sweep alone; from the Python driver, which can evaluate
+    every iterate); stopping rule: change < 1e-4, or the corrections grow.  Wall time is that of
+    the library's driver call (fcn_parareal, one host synchronisation per iteration), with the
+    plans and the workspace already set up."""
     from paper_1507_05988_amd import coarse, fcn
     from paper_1507_05988_amd import workloads as wl
 
@@ -239,15 +241,14 @@ def parareal_measurement(torch):
                 kw.update(channels=m["channels"], bf16=m["bf16"], kappa=m["kappa"], s_ref=m["s_ref"])
             params = m["params"] if m is not None else None
             _, hist = coarse.parareal(inst, params, reference=ref, **kw)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            coarse.parareal(inst, params, **kw)
-            torch.cuda.synchronize()
-            tp = time.perf_counter() - t0
+            coarse.parareal_native(inst, params, **kw)  # warm-up
+            _, nat = coarse.parareal_native(inst, params, **kw)
+            tp = nat["seconds"]
             out[name] = {"seconds": round(tp, 6), "value": round(work / tp, 1), "vs_fp64_plain": round(t64 / tp, 3),
                          "iterations": [{"k": h["iter"], "error": h["error"],
                                          "change": h["change"] if h["iter"] else None} for h in hist],
-                         "status": hist[-1].get("status"), "final_error": hist[-1]["error"]}
+                         "status": hist[-1].get("status"), "final_error": hist[-1]["error"],
+                         "native_driver": {"status": nat["status"], "iterations": nat["iterations"]}}
             if m is not None:
                 out[name]["weights"] = os.path.relpath(wfile, ROOT)
         res[label] = out

@@ -252,6 +252,46 @@ fcn_status fcn_net_destroy(fcn_net_t net);
 fcn_status fcn_parareal_update(const void *g_new, const void *f_old, const void *g_old, const void *u_prev,
                                void *u_new, int32_t nr, int32_t nt, double *part_dev, int32_t nparts, void *stream);
 
+/* Parareal along z for one pulse (not in the paper; an addition of this project).
+ * The pulse is cut into `windows` windows of `steps_per_window` FCN steps.  Iteration 0 is the
+ * coarse sweep U_{j+1} = G(U_j); iteration k runs the fine steps of every window from U^{k-1}
+ * in one batched plan, then the sequential sweep U_{j+1}^k = G(U_j^k) + F(U_j^{k-1}) -
+ * G(U_j^{k-1}).  G = one step of the `coarse` plan (its instance is the pulse with dz = the
+ * window length), plus the network's correction (fcn_net_apply with `sample_dev[0]`: field_off
+ * = coarse_off = 0 and the network's scales) when `net` is not NULL.  The fine FCN judges the
+ * iteration: it stops when the r-weighted relative change max_j |U_{j+1}^k - U_{j+1}^{k-1}| /
+ * |U_{j+1}^k| falls below tol (converged), when it grows and judge != 0 (diverging; U^{k-1} is
+ * kept), or when it is not finite (U^{k-1} is kept).  Without convergence, with fallback != 0
+ * and a `fine_serial` plan (one instance, dz of the fine steps), U is replaced by the serial
+ * fine solution.
+ * Plans: `fine` holds `windows` instances of the pulse back to back; `coarse` and
+ * `fine_serial` one; all FP32 or FP32 storage (complex64 fields), bound to one stream, as is
+ * the network (bound for at least one nr x nt window).  u_dev: [windows + 1][nr][nt]
+ * complex64, U_0 in, U_1..U_windows out.  workspace: fcn_parareal_workspace_size bytes,
+ * 256-byte aligned, caller-owned.  Synchronous: returns when the result is final.
+ * Errors: FCN_E_ARG, FCN_E_SIZE (workspace or plan sizes), FCN_E_STATE (unbound plan),
+ * FCN_E_UNSUPPORTED (an FP64 plan), FCN_E_HIP. */
+#define FCN_PARAREAL_MAX_ITER 64
+enum { FCN_PARAREAL_CONVERGED = 0, FCN_PARAREAL_DIVERGING = 1, FCN_PARAREAL_NONFINITE = 2, FCN_PARAREAL_KMAX = 3,
+       FCN_PARAREAL_FALLBACK = 4 };
+typedef struct {
+    int32_t windows, steps_per_window;
+    int32_t kmax;        /* iterations after the coarse sweep, 0..FCN_PARAREAL_MAX_ITER */
+    int32_t judge;       /* stop when the change grows */
+    int32_t fallback;    /* serial fine solution without convergence (needs fine_serial) */
+    int32_t reserved;    /* must be 0 */
+    double tol;          /* convergence threshold on the change */
+} fcn_parareal_options;
+typedef struct {
+    int32_t iterations;  /* accepted fine iterations (the state U is that of this iteration) */
+    int32_t status;      /* FCN_PARAREAL_* */
+    double change[FCN_PARAREAL_MAX_ITER + 1];  /* change of iteration k (k = 0: +inf) */
+} fcn_parareal_result;
+fcn_status fcn_parareal_workspace_size(int32_t nr, int32_t nt, int32_t windows, size_t *bytes);
+fcn_status fcn_parareal(fcn_plan_t fine, fcn_plan_t coarse, fcn_net_t net, const fcn_net_sample *sample_dev,
+                        fcn_plan_t fine_serial, int32_t nr, int32_t nt, void *u_dev, void *workspace,
+                        size_t workspace_bytes, const fcn_parareal_options *opt, fcn_parareal_result *result);
+
 #ifdef __cplusplus
 }
 #endif

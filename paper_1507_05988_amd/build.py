@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfcn.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["row_kernel.hip", "col_kernel.hip", "runtime.cpp", "net_kernels.hip", "net_runtime.cpp"]
+SOURCES = ["row_kernel.hip", "col_kernel.hip", "runtime.cpp", "net_kernels.hip", "net_runtime.cpp", "parareal.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -278,7 +278,8 @@ def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per
     returned instead.  Returns (fields at the window boundaries U[0..windows], history);
     history[k] = dict(iter, change, error (vs `reference[j]` for U[j+1] if given), seconds);
     iteration 0 is the coarse sweep alone.  The last record carries `status`: "converged",
-    "diverging", "kmax" or "fallback".  `precision` ("fp32" or "fp32_storage") is that of the
+    "diverging", "nonfinite" (a NaN or Inf change; the iterate is discarded), "kmax" or
+    "fallback".  `precision` ("fp32" or "fp32_storage") is that of the
     fine and classical coarse FCN steps; fields are complex64 either way."""
     import torch
 
@@ -334,8 +335,12 @@ def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per
             if rc != fcn.FCN_OK:
                 raise fcn.FcnError(rc, "parareal update")
             p = parts.view(256, 2).sum(0).cpu().numpy()
-            change = max(change, math.sqrt(p[0] / max(p[1], 1e-300)))
+            c = math.sqrt(p[0] / max(p[1], 1e-300)) if math.isfinite(p[0]) and math.isfinite(p[1]) else math.nan
+            change = math.nan if math.isnan(c) or math.isnan(change) else max(change, c)  # NaN is kept
             Gold[j].copy_(gnew)
+        if not math.isfinite(change):  # a non-finite coarse or fine result: never accept it
+            status = "nonfinite"
+            break
         if judge and change > prev_change:  # growing corrections: keep U^{k-1}
             status = "diverging"
             if history:
@@ -359,6 +364,53 @@ def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per
     elif "status" not in history[-1]:
         history[-1]["status"] = status
     return U, history
+
+
+def parareal_native(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS,
+                    steps_per_window=wl.PARAREAL_STEPS_PER_WINDOW, kmax=None, tol=1e-4, channels=32, bf16=True,
+                    kappa=1.0, fallback=True, judge=True, precision="fp32", s_ref=S_REF, stream=None):
+    """Parareal by the library's own driver (fcn_parareal; same iteration, judge and fallback as
+    `parareal`, one host synchronisation per iteration).  Returns (U as a [windows + 1, nr*nt]
+    complex64 tensor, dict(iterations, status, change, seconds)), seconds the wall time of the
+    fcn_parareal call alone."""
+    import torch
+
+    kmax = windows if kmax is None else kmax
+    nr, nt = int(inst["nr"]), int(inst["nt"])
+    fine = fcn.Plan([inst] * windows, precision=precision, stream=stream)
+    st = fine.stream
+    c = dict(inst, dz=inst["dz"] * steps_per_window)
+    crs = fcn.Plan(c, precision=precision, stream=st)
+    serial = fcn.Plan(inst, precision=precision, stream=st) if fallback else None
+    lib = fine.lib
+    net = None
+    smp = None
+    if net_params is not None:
+        net = CoarseNet(channels=channels, bf16=bf16, max_batch=1, max_h=nr, max_w=nt, training=False,
+                        params=net_params, stream=st)
+        smp = samples_tensor(torch, fine.device, [(0, 0, 0, 0, 1.0 / s_ref, kappa * s_ref)])
+    U = torch.zeros((windows + 1, nr * nt), dtype=torch.complex64, device=fine.device)
+    U[0].copy_(torch.from_numpy(wl.gaussian_field(inst, np.complex64).reshape(-1)))
+    nbytes = ctypes.c_size_t()
+    rc = lib.fcn_parareal_workspace_size(nr, nt, windows, ctypes.byref(nbytes))
+    if rc != fcn.FCN_OK:
+        raise fcn.FcnError(rc, "fcn_parareal_workspace_size")
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=fine.device)
+    ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+    opt = fcn.PararealOptions(windows, steps_per_window, kmax, int(judge), int(fallback), 0, float(tol))
+    res = fcn.PararealResult()
+    torch.cuda.synchronize(fine.device)
+    t0 = time.perf_counter()
+    rc = lib.fcn_parareal(fine._h, crs._h, net._h if net is not None else None,
+                          ctypes.c_void_p(smp.data_ptr()) if smp is not None else None,
+                          serial._h if serial is not None else None, nr, nt, ctypes.c_void_p(U.data_ptr()),
+                          ctypes.c_void_p(ws_ptr), nbytes.value, ctypes.byref(opt), ctypes.byref(res))
+    seconds = time.perf_counter() - t0  # the call is synchronous
+    if rc != fcn.FCN_OK:
+        raise fcn.FcnError(rc, "fcn_parareal")
+    out = {"iterations": res.iterations, "status": fcn.PARAREAL_STATUS[res.status],
+           "change": [res.change[k] for k in range(1, kmax + 1)], "seconds": seconds}
+    return U, out
 
 
 def _werr(a, ref, nr, nt):

@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) conv5_kernel(const AI *__restrict__ in, c
                     const int x = x0 + 4 * q + j;
                     if (x < Wout) {
                         float v = acc[j][c] + bv;
-                        if (relu) v = fmaxf(v, 0.0f);
+                        if (relu && v < 0.0f) v = 0.0f;  // NaN propagates
                         st_act(out, (((size_t)b * Cout + co) * Hout + y) * Wout + x, v);
                     }
                 }
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) conv5_mfma_kernel(const bf16_t *__restric
                     for (int i = 0; i < 4; i++) {
                         const int co = 16 * ct + 4 * kg + i;
                         float v = acc[pt][ct][i] + bias[co];
-                        if (relu) v = fmaxf(v, 0.0f);
+                        if (relu && v < 0.0f) v = 0.0f;  // NaN propagates
                         out[(((size_t)b * MF_COUT + co) * Hout + y) * Wout + x].v = bf16_rne(v);
                     }
             }

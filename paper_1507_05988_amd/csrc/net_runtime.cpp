@@ -123,6 +123,10 @@ fcn_status check_dims(fcn_net_t n, int B, int H, int W) {
 
 }  // namespace
 
+namespace fcn {
+hipStream_t net_stream(fcn_net_t n) { return n->stream; }
+}  // namespace fcn
+
 extern "C" {
 
 fcn_status fcn_net_create(int32_t channels, int32_t act_bf16, fcn_net_t *out) {

@@ -576,6 +576,13 @@ fcn_status run_steps(fcn_plan_t p, void *field, int64_t nsteps, double *diag, in
 
 }  // namespace
 
+namespace fcn {
+// accessors for the library's other translation units (parareal driver)
+int plan_precision(fcn_plan_t p) { return p->precision; }
+hipStream_t plan_stream(fcn_plan_t p) { return p->stream; }
+bool plan_bound(fcn_plan_t p) { return p->bound; }
+}  // namespace fcn
+
 extern "C" {
 
 fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_options *opt, fcn_plan_t *out) {

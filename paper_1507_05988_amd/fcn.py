@@ -29,7 +29,10 @@ EXPORTED = (
     "fcn_net_create", "fcn_net_param_count", "fcn_net_workspace_size", "fcn_net_bind", "fcn_net_refresh",
     "fcn_net_input", "fcn_net_forward", "fcn_net_target", "fcn_net_loss", "fcn_net_backward", "fcn_net_adam",
     "fcn_net_apply", "fcn_net_last_error", "fcn_net_destroy", "fcn_parareal_update",
+    "fcn_parareal_workspace_size", "fcn_parareal",
 )
+PARAREAL_MAX_ITER = 64
+PARAREAL_STATUS = {0: "converged", 1: "diverging", 2: "nonfinite", 3: "kmax", 4: "fallback"}
 
 
 class FcnError(RuntimeError):
@@ -49,6 +52,17 @@ class Instance(ctypes.Structure):
         ("dz", ctypes.c_double),
         ("terms", ctypes.c_uint32),
     ]
+
+
+class PararealOptions(ctypes.Structure):
+    _fields_ = [("windows", ctypes.c_int32), ("steps_per_window", ctypes.c_int32), ("kmax", ctypes.c_int32),
+                ("judge", ctypes.c_int32), ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
+
+
+class PararealResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("change", ctypes.c_double * (PARAREAL_MAX_ITER + 1))]
 
 
 class NetSample(ctypes.Structure):
@@ -110,6 +124,9 @@ def load_library(path: str = LIB_PATH):
         "fcn_net_last_error": ([vp], ctypes.c_char_p),
         "fcn_net_destroy": ([vp], ctypes.c_int),
         "fcn_parareal_update": ([vp, vp, vp, vp, vp, i32, i32, vp, i32, vp], ctypes.c_int),
+        "fcn_parareal_workspace_size": ([i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "fcn_parareal": ([vp, vp, vp, vp, vp, i32, i32, vp, vp, ctypes.c_size_t, ctypes.POINTER(PararealOptions),
+                          ctypes.POINTER(PararealResult)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -6,6 +6,7 @@ with cosine similarity >= 0.999.  Parareal is checked for its defining propertie
 G = F it converges in one iteration to the serial fine solution; after as many iterations
 as windows every window is the fine propagation of the previous one (finite termination);
 the judge falls back to the serial fine solution."""
+import math
 import sys
 
 import numpy as np
@@ -270,3 +271,54 @@ def test_mfma_layers_match_reference_and_vector_path(H, W):
     e_mv = np.linalg.norm(outs[True] - outs[False]) / np.linalg.norm(ref)
     say(f"  {H}x{W}: MFMA vs FP64 {e_m:.2e}, vector vs FP64 {e_v:.2e}, MFMA vs vector {e_mv:.2e}")
     assert e_m < 1e-2 and e_v < 1e-2 and e_mv < 1e-2
+
+
+def test_parareal_falls_back_on_corrupted_network_weights():
+    """A NaN weight makes every learned coarse result non-finite: the judge rejects the iterate
+    and the serial fine solution is returned."""
+    import torch
+    inst = _small_inst()
+    nw, spw = 4, 8
+    ref = coarse.serial_fine(inst, windows=nw, steps_per_window=spw)
+    p = coarse.init_params(4, seed=3)
+    p[100] = np.nan  # a first-layer weight: the NaN runs through the CReLU layers
+    U, hist = coarse.parareal(inst, p, windows=nw, steps_per_window=spw, kmax=3, tol=1e-6, reference=None,
+                              channels=4, kappa=1e-6)
+    assert hist[-1]["status"] == "fallback"
+    for j in range(nw):
+        assert torch.equal(U[j + 1], ref[j])
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_native_parareal_driver_matches_python_driver(learned):
+    """fcn_parareal (the library's driver) and the Python driver run the same iteration: same
+    status and number of iterations, bit-identical windows."""
+    import torch
+    inst = wl.config_parareal_trajectory(2001, nr=64, nt=256)
+    nw, spw = 5, 20
+    p = coarse.init_params(4, seed=3) if learned else None
+    kw = dict(windows=nw, steps_per_window=spw, kmax=3, tol=0.0, channels=4, kappa=1e-5, precision="fp32_storage",
+              judge=False, fallback=False)
+    U_py, hist = coarse.parareal(inst, p, **kw)
+    U_c, res = coarse.parareal_native(inst, p, **kw)
+    say(f"  python: {hist[-1]['status']} after {len(hist) - 1} records; native: {res['status']}, "
+        f"{res['iterations']} iterations, changes {[f'{c:.1e}' for c in res['change'][:4]]}")
+    assert res["status"] == hist[-1]["status"] == "kmax" and res["iterations"] == 3
+    for k in range(3):
+        assert abs(res["change"][k] / hist[k + 1]["change"] - 1) < 1e-12
+    for j in range(nw + 1):
+        assert torch.equal(U_c[j], U_py[j])
+
+
+def test_native_parareal_falls_back_on_nonfinite_network():
+    import torch
+    inst = _small_inst()
+    nw, spw = 4, 8
+    ref = coarse.serial_fine(inst, windows=nw, steps_per_window=spw)
+    p = coarse.init_params(4, seed=3)
+    p[-2] = np.inf  # the output bias
+    U, res = coarse.parareal_native(inst, p, windows=nw, steps_per_window=spw, kmax=3, tol=1e-6, channels=4,
+                                    kappa=1e-6)
+    assert res["status"] == "fallback" and not math.isfinite(res["change"][0])
+    for j in range(nw):
+        assert torch.equal(U[j + 1], ref[j])

@@ -133,3 +133,39 @@ def test_plan_without_gpu_raises():
         pytest.skip("a GPU is present")
     with pytest.raises(fcn.FcnError):
         fcn.Plan(wl.config_small())
+
+
+def test_network_abi_validates_on_host(lib):
+    """fcn_net_*: invalid arguments, an unbound network and an undersized workspace are errors
+    returned before any GPU call."""
+    h = ctypes.c_void_p()
+    assert lib.fcn_net_create(0, 1, ctypes.byref(h)) == fcn.FCN_E_ARG
+    assert lib.fcn_net_create(65, 1, ctypes.byref(h)) == fcn.FCN_E_ARG
+    assert lib.fcn_net_create(8, 3, ctypes.byref(h)) == fcn.FCN_E_ARG
+    assert lib.fcn_net_create(32, 1, ctypes.byref(h)) == fcn.FCN_OK
+    n = ctypes.c_size_t()
+    assert lib.fcn_net_param_count(h, ctypes.byref(n)) == fcn.FCN_OK
+    # 4 layers of 5x5 complex weights and complex biases: 1->32->32->32->1
+    assert n.value == 2 * 25 * (32 + 32 * 32 * 2 + 32) + 2 * (32 * 3 + 1)
+    ws_inf, ws_tr = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fcn_net_workspace_size(h, 4, 64, 64, 0, ctypes.byref(ws_inf)) == fcn.FCN_OK
+    assert lib.fcn_net_workspace_size(h, 4, 64, 64, 1, ctypes.byref(ws_tr)) == fcn.FCN_OK
+    assert ws_tr.value > ws_inf.value > 0
+    assert lib.fcn_net_workspace_size(h, 0, 64, 64, 0, ctypes.byref(ws_inf)) == fcn.FCN_E_ARG
+    # unbound network
+    assert lib.fcn_net_forward(h, 1, 8, 8, None) == fcn.FCN_E_STATE
+    assert lib.fcn_net_refresh(h) == fcn.FCN_E_STATE
+    assert lib.fcn_net_adam(h, 1e-3, 0.9, 0.999, 1e-8) == fcn.FCN_E_STATE
+    # bind: NULL buffers, training without gradients, misaligned or undersized workspace
+    p = ctypes.c_void_p(0x1000)
+    args = (4, 64, 64)
+    assert lib.fcn_net_bind(h, None, None, None, None, p, ws_inf.value, *args, 0, None) == fcn.FCN_E_ARG
+    assert lib.fcn_net_bind(h, p, None, None, None, p, ws_tr.value, *args, 1, None) == fcn.FCN_E_ARG
+    assert lib.fcn_net_bind(h, p, None, None, None, ctypes.c_void_p(0x1010), ws_inf.value, *args, 0,
+                            None) == fcn.FCN_E_ARG
+    assert lib.fcn_net_bind(h, p, None, None, None, p, ws_inf.value - 1, *args, 0, None) == fcn.FCN_E_SIZE
+    assert b"workspace" in lib.fcn_net_last_error(h)
+    assert lib.fcn_net_destroy(h) == fcn.FCN_OK
+    # the parareal combination validates its sizes on the host as well
+    assert lib.fcn_parareal_update(p, p, p, p, p, 0, 16, p, 4, None) == fcn.FCN_E_ARG
+    assert lib.fcn_parareal_update(p, p, p, p, p, 16, 16, p, 0, None) == fcn.FCN_E_ARG

@@ -1,0 +1,70 @@
+"""Fixtures under tests/golden/: the numbers the paper prints (cited there), and regression
+values of the oracle written by tests/golden/make_oracle_regression.py (which calls only
+oracle/)."""
+import importlib.util
+import json
+import math
+import os
+
+import numpy as np
+
+import oracle
+from paper_1507_05988_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+def test_paper_timing_table_is_transcribed_consistently():
+    """Table 2 (Sec. 5.1): the printed speed-up column is the ratio of the printed times."""
+    t = _load("paper_printed_values.json")["timing_table"]
+    for s, tn, sp in zip(t["threads"], t["seconds"], t["speedup"]):
+        assert abs(t["seconds"][0] / tn - sp) < 0.006, (s, t["seconds"][0] / tn, sp)
+
+
+def test_critical_power_uses_the_printed_prefactor():
+    """P_cr = 3.77 lambda0^2 / (8 pi n0 n2) (Sec. 2): the input builder's power scale."""
+    c = _load("paper_printed_values.json")["critical_power"]["prefactor"]
+    for lam, n0, n2 in ((800e-9, 1.0, 3.2e-23), (800e-9, 1.0, 1e-23), (400e-9, 1.0003, 5e-23)):
+        assert math.isclose(wl.critical_power(lam, n0, n2), c * lam ** 2 / (8 * math.pi * n0 * n2), rel_tol=1e-15)
+
+
+def test_printed_multiphoton_coefficient_through_the_oracle():
+    """The paper's beta^(10) = 1.27e-126 cm^17/W^9 (Sec. 2), read in cm units (1 cm^17 =
+    1e-34 m^17) and expressed through sigma_K rho_at = beta / (K hbar omega0): a constant-
+    intensity row loses intensity as I exp(-beta I^(K-1) h) over an oracle half step h."""
+    m = _load("paper_printed_values.json")["multiphoton_coefficient"]
+    K, lam = m["K"], m["lambda0_m"]
+    beta = m["beta_K_cm"] * 1e-34
+    hbar, c = 1.054571817e-34, 299792458.0
+    w0 = 2 * math.pi * c / lam
+    rho_at = 5.4e24
+    inst = wl.config_full(nr=4, nt=16)
+    inst.update(K=K, lambda0=lam, sigma_K=beta / (K * hbar * w0 * rho_at), rho_at=rho_at, terms=wl.MPA)
+    h = 1e-3
+    intensity = (0.1 / (beta * h)) ** (1.0 / (K - 1))  # beta I^(K-1) h = 0.1
+    a = np.full((4, 16), math.sqrt(intensity), dtype=np.complex128)
+    a[-1] = 0
+    out = oracle.nl_half(inst, a, h)
+    got = np.abs(out[0, 0]) ** 2 / intensity
+    assert math.isclose(got, math.exp(-0.1), rel_tol=1e-12), got
+
+
+def test_oracle_matches_its_regression_values():
+    g = _load("oracle_regression.json")
+    spec = importlib.util.spec_from_file_location("make_oracle_regression", os.path.join(GOLDEN, "make_oracle_regression.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert mod.source_hash() == g["oracle_source_sha256"], \
+        "the oracle's source changed: regenerate tests/golden/oracle_regression.json in a commit that names why"
+    now = mod.compute()
+    for name, ref in g["cases"].items():
+        cur = now[name]
+        for key in ("energy", "i_max", "i_axis", "rho_max", "phi"):
+            assert math.isclose(cur[key], ref[key], rel_tol=1e-12, abs_tol=1e-300), (name, key)
+        assert np.allclose(cur["fluence_first_8"], ref["fluence_first_8"], rtol=1e-12)
+        assert np.allclose(cur["field_row0_first_4"], ref["field_row0_first_4"], rtol=1e-12, atol=0)

@@ -133,6 +133,40 @@ def batched_sweep_measurement(torch):
                                   "unit": "GB/s", "frac": round(byt / (kcol * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
+def paper_shapes_measurement(torch):
+    """The paper's own grids, as context beside its CPU numbers (Sec. 5.1 Table 2 and Sec. 5.2;
+    the values come from tests/golden/paper_printed_values.json).  The paper's runs are FP64 on
+    an Intel Xeon with Pthreads and state no physics for the timing example; the comparison is
+    of wall time for the same grid and step count, not of a like-for-like machine."""
+    from paper_1507_05988_amd import autotune, fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    with open(os.path.join(ROOT, "tests", "golden", "paper_printed_values.json")) as fh:
+        paper = json.load(fh)
+    out = {}
+    t2 = paper["timing_table"]
+    cases = (("timing_example", wl.config_paper_timing(), t2["grid"]["Nz"], 1000,
+              {"paper_seconds_1_thread": t2["seconds"][0], "paper_seconds_20_threads": t2["seconds"][-1]}),
+             ("application_1p1km", wl.config_paper_application(), int(paper["application_run"]["Nz"]), 1000,
+              {"paper_statement": "under 3 days with 20 threads, about two months serially (Sec. 5.2)"}))
+    for name, inst, nz, timed, ctx in cases:
+        pts = int(inst["nr"]) * int(inst["nt"])
+        rec = {"grid": f"{inst['nr']}x{inst['nt']}", "steps_in_paper": nz, "timed_steps": timed, **ctx}
+        for prec in ("fp64", "fp32"):
+            t = autotune.tune(inst, prec, steps=10, repeats=2)
+            plan = fcn.Plan(inst, precision=prec, col_tile=t["col_tile"], col_rows=t["col_rows"])
+            a0 = wl.gaussian_field(inst)
+            init = plan.pack(a0 if prec == "fp64" else a0.astype(np.complex64))
+            f = init.clone()
+            plan.step(f, 5)
+            sec = timed_steps(plan, f, init, timed, torch)
+            plan.sync()
+            rec[prec] = {"seconds_per_step": sec / timed, "seconds_for_paper_steps": sec / timed * nz,
+                         "value": round(pts * timed / sec, 1), "col_tile": [t["col_tile"], t["col_rows"]]}
+        out[name] = rec
+    return out
+
+
 def coarse_net_measurement(torch):
     """The learned coarse network (C = 32): full-grid forward on one 512 x 2048 window (the
     inference of one coarse step; 4.4e11 flop counting a complex multiply-add as 4 real ones)
@@ -267,6 +301,7 @@ def main():
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--no-net", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-paper-shapes", action="store_true")
     ap.add_argument("--only-net", action="store_true",
                     help="only the learned coarse network's inference and training rates (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -440,6 +475,8 @@ def main():
 
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep_measurement(torch)
+    if not args.no_paper_shapes:
+        out["paper_shapes"] = paper_shapes_measurement(torch)
     if not args.no_parareal:
         out["parareal"] = parareal_measurement(torch)
     if not args.no_net:

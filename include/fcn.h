@@ -66,7 +66,7 @@ enum { FCN_FP64 = 0, FCN_FP32 = 1, FCN_FP32_STORAGE = 2 };
 
 /* One pulse and its grid. */
 typedef struct {
-    int32_t nr;              /* radial points, 3 <= nr <= 2048; row nr-1 is r = r_max (A = 0) */
+    int32_t nr;              /* radial points, 3 <= nr <= 4096; row nr-1 is r = r_max (A = 0) */
     int32_t nt;              /* time points, a power of two in [64, 8192] */
     double r_max;            /* [m] */
     double t_min, t_max;     /* [s]; periodic window, t_max excluded */
@@ -91,7 +91,7 @@ typedef struct {
     double max_phase;        /* [rad] per step, adaptive mode */
     double dz_min, dz_max;   /* [m], adaptive mode */
     int32_t use_graph;       /* 1: replay the step body as a captured HIP graph */
-    int32_t col_tile;        /* 0: auto; else frequencies per column workgroup (4, 8, 16 or 32) */
+    int32_t col_tile;        /* 0: auto; else frequencies per column workgroup (1, 2, 4, 8, 16 or 32) */
     int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (8 or 16) */
     int32_t reserved;        /* must be 0 */
 } fcn_options;

@@ -245,6 +245,10 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
 template <typename R, typename ST>
 static hipError_t launch_col_p(int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1) {
+    if (w == 1 && l == 8) return launch_col_t<R, ST, 1, 8>(nr, a, grid, s, e0, e1);
+    if (w == 1 && l == 16) return launch_col_t<R, ST, 1, 16>(nr, a, grid, s, e0, e1);
+    if (w == 2 && l == 8) return launch_col_t<R, ST, 2, 8>(nr, a, grid, s, e0, e1);
+    if (w == 2 && l == 16) return launch_col_t<R, ST, 2, 16>(nr, a, grid, s, e0, e1);
     if (w == 4 && l == 8) return launch_col_t<R, ST, 4, 8>(nr, a, grid, s, e0, e1);
     if (w == 4 && l == 16) return launch_col_t<R, ST, 4, 16>(nr, a, grid, s, e0, e1);
     if (w == 8 && l == 8) return launch_col_t<R, ST, 8, 8>(nr, a, grid, s, e0, e1);

@@ -123,7 +123,7 @@ fcn_status hip_fail(fcn_plan_t p, hipError_t e, const char *what) {
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 const char *check_instance(const fcn_instance &in) {
-    if (in.nr < 3 || in.nr > 2048) return "nr must be in [3, 2048]";
+    if (in.nr < 3 || in.nr > 4096) return "nr must be in [3, 4096]";
     if (!is_pow2(in.nt) || in.nt < 64 || in.nt > 8192) return "nt must be a power of two in [64, 8192]";
     if (!(in.r_max > 0.0) || !std::isfinite(in.r_max)) return "r_max must be positive";
     if (!(in.t_max > in.t_min) || !std::isfinite(in.t_max) || !std::isfinite(in.t_min)) return "t_max must exceed t_min";
@@ -199,17 +199,19 @@ void round_unit_f32(double c, double s, float out[2]) {
 }
 
 bool col_tiles_supported(int w, int l) {
-    return (w == 4 && (l == 8 || l == 16)) || (w == 8 && (l == 8 || l == 16)) || (w == 16 && (l == 8 || l == 16)) ||
-           (w == 32 && l == 8);
+    return ((w == 1 || w == 2 || w == 4 || w == 8 || w == 16) && (l == 8 || l == 16)) || (w == 32 && l == 8);
 }
 
 // Column tile choice: frequencies per workgroup W and rows per thread L.
 void choose_col_tiles(int precision, int nr, const fcn_options &opt, int &w, int &l) {
     l = opt.col_rows ? opt.col_rows : (precision == FCN_FP32 ? 16 : 8);
     w = opt.col_tile ? opt.col_tile : 4;
-    // keep the workgroup within 512 threads
+    // keep the workgroup within 512 threads: fewer frequencies per workgroup first (down to 4,
+    // which keeps 32-byte row segments), then 16 rows per thread, then 2 and 1 frequencies
+    // (tall columns, nr > 2048 with 16 rows or nr > 1024 with 8)
     while (w * ((nr + l - 1) / l) > 512 && w > 4) w /= 2;
-    while (w * ((nr + l - 1) / l) > 512 && l < 16) l *= 2;
+    while (w * ((nr + l - 1) / l) > 512 && l < 16 && opt.col_rows == 0 && precision == FCN_FP32) l *= 2;
+    while (w * ((nr + l - 1) / l) > 512 && w > 1) w /= 2;
 }
 
 fcn_status build_plan(fcn_plan_t p) {
@@ -604,8 +606,8 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
             return FCN_E_ARG;
         }
     }
-    if (p->opt.col_tile && p->opt.col_tile != 4 && p->opt.col_tile != 8 && p->opt.col_tile != 16 &&
-        p->opt.col_tile != 32) {
+    if (p->opt.col_tile && p->opt.col_tile != 1 && p->opt.col_tile != 2 && p->opt.col_tile != 4 &&
+        p->opt.col_tile != 8 && p->opt.col_tile != 16 && p->opt.col_tile != 32) {
         delete p;
         return FCN_E_ARG;
     }
@@ -621,7 +623,7 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
         const char *why = check_instance(inst[i]);
         if (why) {
             delete p;
-            return (inst[i].nr > 2048 || inst[i].nt > 8192) ? FCN_E_SIZE : FCN_E_ARG;
+            return (inst[i].nr > 4096 || inst[i].nt > 8192) ? FCN_E_SIZE : FCN_E_ARG;
         }
         if (!p->opt.adaptive && !(inst[i].dz > 0.0)) {
             delete p;

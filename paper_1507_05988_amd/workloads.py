@@ -183,6 +183,23 @@ LEARNED_WINDOWS = 8
 LEARNED_STEPS_PER_WINDOW = 250
 
 
+def config_paper_timing(nr=2112, nt=2048) -> dict:
+    """The grid of the paper's timing example (Sec. 5.1, Table 2: Nr = 2112, Nt = 2048, 1000
+    steps); the paper gives no physics or ranges for it, so the full-model pulse's are used
+    (r in [0, 8 mm], t in [-400, 400) fs, w0 = 2 mm, tau = 100 fs, 5 Pcr, dz = 5 mm)."""
+    return config_full(nr=nr, nt=nt)
+
+
+def config_paper_application(nr=1350, nt=1024) -> dict:
+    """The paper's 1.1 km run (Sec. 5.2): I0 = 3.14e14 W/m^2, r0 = 18 mm, tau0 = 300 fs, C = 0,
+    Nr = 1350, Nt = 1024, 1.1e6 steps (dz = 1 mm).  Unstated and read here: r in [0, 4 r0],
+    t in [-4 tau0, 4 tau0), the full-model coefficient set."""
+    inst = _base(nr, nt, 18 * MM, 300 * FS, dz=1e-3, **FULL_PHYSICS)
+    pcr = critical_power(inst["lambda0"], inst["n0"], inst["n2"])
+    power = 3.14e14 * math.pi * (18 * MM) ** 2 / 2.0  # I0 = 2P / (pi r0^2)
+    return _pulse(inst, 18 * MM, 300 * FS, power / pcr)
+
+
 def random_field(nr: int, nt: int, seed: int, scale: float = 1.0, dtype=np.complex128) -> np.ndarray:
     """Seeded complex normal field (stage tests on random spectra); last row zero."""
     rng = np.random.default_rng(seed)

@@ -65,7 +65,7 @@ def test_fft_stages(precision, nt):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("nr", [3, 4, 8, 37, 128, 512, 1024, 2048])
+@pytest.mark.parametrize("nr", [3, 4, 8, 37, 128, 512, 1024, 2048, 2112, 4096])
 def test_cn_stage(precision, nr):
     say(f"cn stage {precision} nr={nr}")
     nt = 64
@@ -77,13 +77,14 @@ def test_cn_stage(precision, nr):
         plan.stage(fcn.STAGE_CN, f, dz)
         got = plan.unpack(f)[0]
         want = oracle.cn_columns(inst, a, dz)
-        tol = 1e-12 if precision == "fp64" else 2e-5
+        # FP32: the partitioned solve's reduced system has 2 nr / 16 unknowns per column
+        tol = 1e-12 if precision == "fp64" else 2e-5 * max(1.0, nr / 2048)
         assert relmax(got, want) < tol, (dz, relmax(got, want))
     plan.sync()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("tiles", [(8, 8), (16, 16), (4, 16), (32, 8), (16, 8)])
+@pytest.mark.parametrize("tiles", [(8, 8), (16, 16), (4, 16), (32, 8), (16, 8), (2, 8), (2, 16), (1, 8), (1, 16)])
 def test_cn_stage_tiles(precision, tiles):
     nr, nt = 120, 128  # W * ceil(nr/L) stays within 512 threads for every tile
     if precision == "fp64" and tiles[1] == 16:
@@ -445,3 +446,16 @@ def test_fp32_storage_batch_and_graph():
     for i, inst in enumerate(insts):
         single, _ = _run(inst, "fp32_storage", 37, a0=fields[i])
         assert np.array_equal(got[i], single)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 10 * 1e-6)])
+def test_paper_grid_nr_2112(precision, tol):
+    """The radial size of the paper's timing example (Nr = 2112, Table 2): tall columns solved
+    with 2 (FP32) or 1 (FP64) frequencies per workgroup, 10 full-model steps against the oracle."""
+    inst = wl.config_full(nr=2112, nt=128)
+    a0 = wl.gaussian_field(inst) * math.sqrt(5e17 / inst["I0"])
+    got, plan = _run(inst, precision, 10, a0=a0 if precision == "fp64" else a0.astype(np.complex64))
+    want = oracle.propagate(inst, a0 if precision == "fp64" else a0.astype(np.complex64).astype(np.complex128), 10)
+    e = werr(got.astype(np.complex128), want)
+    say(f"  2112 x 128 {precision} tiles {plan.tiles()}: {e:.3e}")
+    assert e < tol

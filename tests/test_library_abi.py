@@ -69,7 +69,7 @@ def test_plan_sizes_on_host(lib):
     ("nt", 100, fcn.FCN_E_ARG),          # not a power of two
     ("nt", 16384, fcn.FCN_E_SIZE),       # beyond the largest FFT
     ("nr", 2, fcn.FCN_E_ARG),
-    ("nr", 4096, fcn.FCN_E_SIZE),
+    ("nr", 4097, fcn.FCN_E_SIZE),
     ("r_max", -1.0, fcn.FCN_E_ARG),
     ("t_max", -1.0, fcn.FCN_E_ARG),
     ("K", 0, fcn.FCN_E_ARG),

@@ -9,13 +9,15 @@ precision with FP64 density scan and diagnostics.  One step is one whole Strang 
 partials included) on the resident field.  The timed steps run in chunks of at most
 500 steps (z <= 2.5 m, before the collapse near 4.2 m), each chunk starting from the
 resident initial pulse: past the collapse the trajectory is chaotic and the explicit RK4
-density step can leave its stability region (sigma_K I^K dtau > 2.785), see the design doc.
+density step can leave its stability region (sigma_K I^K dtau > 2.785).
 The line also carries the FP64 plain method and the FP32-storage mode (FP32 field, FP64
 arithmetic) on the same workload, the FP32 and FP32-storage errors against FP64 at
 checkpoints (with the FP64 run's own sensitivity to FP32 input rounding as the
 conditioning floor), parareal along z on a held-out learned-coarse trajectory (classical
-and learned coarse propagator, against the serial FP64 plain method), the roofline of the
-dominant kernel and the CPU oracle's rate on the host.
+and learned coarse propagator, against the serial FP64 plain method), the long-distance
+pulse (1024 x 8192, adaptive dz) at checkpoints up to 10^4 steps (FP32 modes against FP64,
+FP64 against the CPU oracle's stored values; --long-pulse-checkpoints extends it), the
+roofline of the dominant kernel and the CPU oracle's rate on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -167,6 +169,92 @@ def paper_shapes_measurement(torch):
     return out
 
 
+def long_pulse_measurement(torch, checkpoints):
+    """Long-distance pulse 1024 x 8192, full model, adaptive dz (0.05 rad): FP64 adaptive run;
+    FP32, FP32 storage and an FP64 run from the FP32-rounded input (the floor: what the
+    trajectory itself makes of FP32 input rounding) replay its dz log.  Errors against the
+    FP64 GPU run at every checkpoint; the FP64 run against the CPU oracle's stored values
+    (tests/golden/long_pulse_reference.json, written by a script that calls only the oracle)
+    at the checkpoints the oracle covers."""
+    from paper_1507_05988_amd import fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    with open(os.path.join(ROOT, "tests", "golden", "long_pulse_reference.json")) as fh:
+        oracle_ref = {c["steps"]: c for c in json.load(fh)["checkpoints"]}
+    inst = wl.config_long()
+    pts = int(inst["nr"]) * int(inst["nt"])
+    a0 = wl.gaussian_field(inst)
+    a32 = a0.astype(np.complex64)
+    kw = dict(adaptive=True, max_phase=wl.LONG_MAX_PHASE, dz_min=wl.LONG_DZ_MIN, dz_max=wl.LONG_DZ_MAX)
+    p64 = fcn.Plan(inst, precision="fp64", **kw)
+    runs = {"floor": fcn.Plan(inst, precision="fp64"), "fp32": fcn.Plan(inst, precision="fp32"),
+            "fp32_storage": fcn.Plan(inst, precision="fp32_storage")}
+    g64 = p64.pack(a0)
+    g = {"floor": runs["floor"].pack(a32.astype(np.complex128)), "fp32": runs["fp32"].pack(a32),
+         "fp32_storage": runs["fp32_storage"].pack(a32)}
+    log = torch.zeros(checkpoints[-1], dtype=torch.float64, device=p64.device)
+    ms = {"fp64": 0.0, "floor": 0.0, "fp32": 0.0, "fp32_storage": 0.0}
+    alive = {k: True for k in runs}
+    rows = []
+    done = 0
+
+    def timed(key, fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ms[key] += e0.elapsed_time(e1)
+
+    for cp in checkpoints:
+        n = cp - done
+        timed("fp64", lambda: p64.propagate(g64, n, dz_log=log[done:cp]))
+        p64.sync()
+        for name, p in runs.items():
+            if not alive[name]:
+                continue
+            timed(name, lambda: p.propagate(g[name], n, dz_log=log[done:cp], replay=True))
+            try:
+                p.sync()
+            except fcn.FcnError:
+                alive[name] = False
+        done = cp
+        lg = log[:cp].cpu().numpy()
+        x64 = p64.unpack(g64)[0]
+        d64 = p64.split_diag(p64.diagnostics(g64))[0]
+        row = {"steps": cp, "z_m": round(float(lg.sum()), 4), "dz_last": float(lg[-1]), "dz_min": float(lg.min()),
+               "i_max_fp64": d64["i_max"], "rho_max_fp64": d64["rho_max"]}
+        row["floor_fp64_from_fp32_input"] = (weighted_rel_err(runs["floor"].unpack(g["floor"])[0], x64)
+                                             if alive["floor"] else None)
+        for name in ("fp32", "fp32_storage"):
+            if not alive[name]:
+                row[name] = None
+                continue
+            p = runs[name]
+            d = p.split_diag(p.diagnostics(g[name]))[0]
+            row[name] = {"field": weighted_rel_err(p.unpack(g[name])[0].astype(np.complex128), x64),
+                         "fluence": float(np.max(np.abs(d["fluence"] - d64["fluence"])) / np.max(d64["fluence"])),
+                         "rho_max": abs(d["rho_max"] - d64["rho_max"]) / max(d64["rho_max"], 1e-300),
+                         "energy": abs(d["energy"] / d64["energy"] - 1)}
+        c = oracle_ref.get(cp)
+        if c is not None:
+            smp = np.array([x64[m, t] for m, t, _, _ in c["field_samples"]])
+            want = np.array([complex(re, im) for _, _, re, im in c["field_samples"]])
+            flu = np.asarray(d64["fluence"][::c["fluence_stride"]])
+            row["fp64_vs_oracle"] = {
+                "z": abs(float(lg.sum()) / c["z"] - 1),
+                "field_samples": float(np.max(np.abs(smp - want)) / c["abs_max"]),
+                "fluence": float(np.max(np.abs(flu - np.asarray(c["fluence"]))) / max(c["fluence"])),
+                "rho_max": abs(d64["rho_max"] / c["rho_max"] - 1), "energy": abs(d64["energy"] / c["energy"] - 1)}
+        rows.append(row)
+        print(f"long pulse {cp} steps: z = {row['z_m']} m", file=sys.stderr, flush=True)
+    rates = {k: round(pts * checkpoints[-1] / (v / 1e3), 1) for k, v in ms.items() if alive.get(k, True)}
+    return {"grid": f"{inst['nr']}x{inst['nt']}", "checkpoints": rows,
+            "seconds": {k: round(v / 1e3, 3) for k, v in ms.items()},
+            "pt_steps_per_s": {"fp64_adaptive": rates.get("fp64"), "fp32_replay": rates.get("fp32"),
+                               "fp32_storage_replay": rates.get("fp32_storage")}}
+
+
 def coarse_net_measurement(torch):
     """The learned coarse network (C = 32): full-grid forward on one 512 x 2048 window (the
     inference of one coarse step; 4.4e11 flop counting a complex multiply-add as 4 real ones)
@@ -302,6 +390,9 @@ def main():
     ap.add_argument("--no-net", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-paper-shapes", action="store_true")
+    ap.add_argument("--no-long-pulse", action="store_true")
+    ap.add_argument("--long-pulse-checkpoints", default="100,1000,10000",
+                    help="comma-separated step counts of the long-distance pulse checkpoints")
     ap.add_argument("--only-net", action="store_true",
                     help="only the learned coarse network's inference and training rates (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -477,6 +568,8 @@ def main():
         out["batched_sweep"] = batched_sweep_measurement(torch)
     if not args.no_paper_shapes:
         out["paper_shapes"] = paper_shapes_measurement(torch)
+    if not args.no_long_pulse:
+        out["long_pulse"] = long_pulse_measurement(torch, [int(x) for x in args.long_pulse_checkpoints.split(",")])
     if not args.no_parareal:
         out["parareal"] = parareal_measurement(torch)
     if not args.no_net:

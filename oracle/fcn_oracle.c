@@ -16,7 +16,7 @@
  *   - the nonlinear half step integrates the electron density along t with
  *     classical RK4 and multiplies A by exp(dz/2 N) (Sec. 3.2, Eqs. Anhalf,
  *     Anhalf1, ionization, nonlinearpart).
- * Readings where the paper is silent or misprinted (listed in the design doc):
+ * Readings where the paper is silent or misprinted:
  *   - c_j and f_j use (1 + 1/2j): the 1/r term adds +1/(2j dr^2) on A_{j+1}
  *     (derived from Eqs. diff2-diff3; the printed (1 - 1/2j) cancels the 1/r term);
  *   - the plasma term uses omega_pe^2/omega0^2 = rho/rho_c;
@@ -40,7 +40,7 @@
 
 typedef double complex cplx;
 
-/* Term switches (bit values match the public interface documented in the design doc). */
+/* Term switches (the same bit values as the terms mask of the public C interface). */
 #define ORC_DIFFRACTION 1u
 #define ORC_GVD 2u
 #define ORC_KERR 4u

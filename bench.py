@@ -10,8 +10,9 @@ partials included) on the resident field.  The timed steps run in chunks of at m
 500 steps (z <= 2.5 m, before the collapse near 4.2 m), each chunk starting from the
 resident initial pulse: past the collapse the trajectory is chaotic and the explicit RK4
 density step can leave its stability region (sigma_K I^K dtau > 2.785).
-The line also carries the FP64 plain method and the FP32-storage mode (FP32 field, FP64
-arithmetic) on the same workload, the FP32 and FP32-storage errors against FP64 at
+The line also carries the FP64 plain method, the FP32-storage mode (FP32 field, FP64
+arithmetic) and the FP32-CN64 mode (FP32 row pass with twiddle pairs, FP64 column solve) on
+the same workload, the errors of the three FP32-field modes against FP64 at
 checkpoints (with the FP64 run's own sensitivity to FP32 input rounding as the
 conditioning floor), parareal along z on a held-out learned-coarse trajectory (classical
 and learned coarse propagator, against the serial FP64 plain method), the long-distance
@@ -46,24 +47,31 @@ def weighted_rel_err(a, ref):
 
 CHUNK = 500
 ROOT = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_kernel_fullmodel_fp32_512x2048_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fcn_step_fullmodel_512x2048_traffic.json")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused row kernel from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (copy-calibrated), or None when the kernel sources changed since."""
+def measured_traffic(precision, kernel, tiles):
+    """HBM bytes per launch of one kernel of the full-model step (`kernel` "row" or "col") in
+    `precision` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or
+    None when no run covers that kernel or its sources changed since."""
     import hashlib
 
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-        h = hashlib.sha256()
-        for src in t["sources"]:
-            with open(os.path.join(ROOT, src), "rb") as fh:
-                h.update(fh.read())
-        return int(t["bytes_per_launch"]) if h.hexdigest() == t["sources_sha256"] else None
+            entries = json.load(fh)["kernels"]
+        for t in entries:
+            if t["precision"] != precision or t["pass"] != kernel:
+                continue
+            if kernel == "col" and [t["col_tile"], t["col_rows"]] != [tiles["col_tile"], tiles["col_rows"]]:
+                continue
+            h = hashlib.sha256()
+            for src in t["sources"]:
+                with open(os.path.join(ROOT, src), "rb") as fh:
+                    h.update(fh.read())
+            return int(t["bytes_per_launch"]) if h.hexdigest() == t["sources_sha256"] else None
     except (OSError, KeyError, ValueError):
-        return None
+        pass
+    return None
 
 
 def timed_steps(plan, field, init, steps, torch):
@@ -188,12 +196,13 @@ def long_pulse_measurement(torch, checkpoints):
     kw = dict(adaptive=True, max_phase=wl.LONG_MAX_PHASE, dz_min=wl.LONG_DZ_MIN, dz_max=wl.LONG_DZ_MAX)
     p64 = fcn.Plan(inst, precision="fp64", **kw)
     runs = {"floor": fcn.Plan(inst, precision="fp64"), "fp32": fcn.Plan(inst, precision="fp32"),
-            "fp32_storage": fcn.Plan(inst, precision="fp32_storage")}
+            "fp32_storage": fcn.Plan(inst, precision="fp32_storage"),
+            "fp32_cn64": fcn.Plan(inst, precision="fp32_cn64")}
     g64 = p64.pack(a0)
     g = {"floor": runs["floor"].pack(a32.astype(np.complex128)), "fp32": runs["fp32"].pack(a32),
-         "fp32_storage": runs["fp32_storage"].pack(a32)}
+         "fp32_storage": runs["fp32_storage"].pack(a32), "fp32_cn64": runs["fp32_cn64"].pack(a32)}
     log = torch.zeros(checkpoints[-1], dtype=torch.float64, device=p64.device)
-    ms = {"fp64": 0.0, "floor": 0.0, "fp32": 0.0, "fp32_storage": 0.0}
+    ms = {"fp64": 0.0, "floor": 0.0, "fp32": 0.0, "fp32_storage": 0.0, "fp32_cn64": 0.0}
     alive = {k: True for k in runs}
     rows = []
     done = 0
@@ -226,7 +235,7 @@ def long_pulse_measurement(torch, checkpoints):
                "i_max_fp64": d64["i_max"], "rho_max_fp64": d64["rho_max"]}
         row["floor_fp64_from_fp32_input"] = (weighted_rel_err(runs["floor"].unpack(g["floor"])[0], x64)
                                              if alive["floor"] else None)
-        for name in ("fp32", "fp32_storage"):
+        for name in ("fp32", "fp32_storage", "fp32_cn64"):
             if not alive[name]:
                 row[name] = None
                 continue
@@ -252,7 +261,8 @@ def long_pulse_measurement(torch, checkpoints):
     return {"grid": f"{inst['nr']}x{inst['nt']}", "checkpoints": rows,
             "seconds": {k: round(v / 1e3, 3) for k, v in ms.items()},
             "pt_steps_per_s": {"fp64_adaptive": rates.get("fp64"), "fp32_replay": rates.get("fp32"),
-                               "fp32_storage_replay": rates.get("fp32_storage")}}
+                               "fp32_storage_replay": rates.get("fp32_storage"),
+                               "fp32_cn64_replay": rates.get("fp32_cn64")}}
 
 
 def coarse_net_measurement(torch):
@@ -390,6 +400,9 @@ def main():
     ap.add_argument("--no-net", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-paper-shapes", action="store_true")
+    ap.add_argument("--headline-precision", default="fp32_cn64", choices=["fp32_cn64", "fp32"],
+                    help="mode of the headline line: fp32_cn64 (within 1e-5 of FP64 over the timed "
+                         "chunks) or fp32 (faster, within 1e-5 for about 190 steps of this workload)")
     ap.add_argument("--no-long-pulse", action="store_true")
     ap.add_argument("--long-pulse-checkpoints", default="100,1000,10000",
                     help="comma-separated step counts of the long-distance pulse checkpoints")
@@ -432,11 +445,12 @@ def main():
     # ---- FP32 timed region
     from paper_1507_05988_amd import autotune
 
-    tiles = {prec: autotune.tune(inst, prec, steps=50, repeats=3) for prec in ("fp32", "fp64", "fp32_storage")}
+    tiles = {prec: autotune.tune(inst, prec, steps=50, repeats=3) for prec in ("fp32", "fp64", "fp32_storage", "fp32_cn64")}
     tile_kw = {prec: dict(col_tile=t["col_tile"], col_rows=t["col_rows"]) for prec, t in tiles.items()}
     print("[bench] column tiles (autotuned): " + ", ".join(f"{k} {t['col_tile']}x{t['col_rows']}" for k, t in tiles.items()),
           file=sys.stderr, flush=True)
-    p32 = fcn.Plan(inst, precision="fp32", **tile_kw["fp32"])
+    hp = args.headline_precision
+    p32 = fcn.Plan(inst, precision=hp, **tile_kw[hp])
     init32 = p32.pack(a0.astype(np.complex64))
     f32 = init32.clone()
     if args.warmup > 0:
@@ -445,7 +459,7 @@ def main():
     p32.sync()
     value = pts * args.steps / sec
     ms_per_step = sec * 1e3 / args.steps
-    print(f"[bench] fp32 {args.steps} steps in {sec:.4f} s ({ms_per_step * 1e3:.2f} us/step)", file=sys.stderr,
+    print(f"[bench] {hp} {args.steps} steps in {sec:.4f} s ({ms_per_step * 1e3:.2f} us/step)", file=sys.stderr,
           flush=True)
 
     # ---- per-kernel durations with HIP events on the plan's stream
@@ -453,13 +467,16 @@ def main():
     krow, kcol, _ = p32.step_timed(f32, min(args.steps, CHUNK))
     p32.sync()
     bytes_per_launch = pts * 2 * 8  # each pass reads and writes every FP32 complex value once
-    dom_name, dom_ms = ("row_kernel (iFFT + 2 NL half steps + FFT)", krow) if krow >= kcol else \
-        ("col_kernel (CN solve)", kcol)
+    row_name = ("row_kernel<float, float, 2048, 8> (iFFT + 2 NL half steps + FFT"
+                + (", twiddle pairs)" if hp == "fp32_cn64" else ")"))
+    col_name = (f"col_kernel<{'double' if hp == 'fp32_cn64' else 'float'}, float, {tiles[hp]['col_tile']}, "
+                f"{tiles[hp]['col_rows']}> (CN solve)")
+    dom = "row" if krow >= kcol else "col"
+    dom_name, dom_ms = (row_name, krow) if dom == "row" else (col_name, kcol)
     achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic() if krow >= kcol else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_name,
-                "kernel_ms": round(dom_ms, 6), "row_ms": round(krow, 6), "col_ms": round(kcol, 6),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(hp, dom, tiles[hp]),
+                "kernel": dom_name, "kernel_ms": round(dom_ms, 6), "row_ms": round(krow, 6), "col_ms": round(kcol, 6),
                 "bytes_per_launch": bytes_per_launch}
     print(f"[bench] kernel means: row {krow * 1e3:.2f} us, col {kcol * 1e3:.2f} us", file=sys.stderr, flush=True)
 
@@ -474,10 +491,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64" if hp == "fp32_cn64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "full-model pulse, FP32 field / FP64 density, Nr=512, Nt=2048, dz=5 mm, "
-                               f"timed in chunks of {CHUNK} steps from z=0",
+        "config": {"workload": ("full-model pulse, FP32 field, FP32 FFTs (twiddle pairs) and nonlinear step, "
+                                "FP64 CN column solve and density scan" if hp == "fp32_cn64" else
+                                "full-model pulse, FP32 field / FP64 density") +
+                               f", Nr=512, Nt=2048, dz=5 mm, timed in chunks of {CHUNK} steps from z=0",
+                   "precision": hp,
                    "nr": int(inst["nr"]), "nt": int(inst["nt"]), "dz": inst["dz"], "P_over_Pcr": 5.0,
                    "terms": "diffraction+GVD+Kerr(n2,n4)+plasma+MPA(K=8)+collisions"},
         "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1),
@@ -501,18 +521,21 @@ def main():
                              "steps": n64, "row_ms": round(r64, 6), "col_ms": round(c64, 6),
                              "hbm_gbs_algorithmic": round(pts * n64 / s64 * 64 / 1e9, 1)}
         del p64, f64
-        pm = fcn.Plan(inst, precision="fp32_storage", **tile_kw["fp32_storage"])
-        initm = pm.pack(a0.astype(np.complex64))
-        fm = initm.clone()
-        pm.step(fm, min(args.warmup, 50) or 1)
-        sm = timed_steps(pm, fm, initm, n64, torch)
-        pm.sync()
-        fm.copy_(initm)
-        rm, cm, _ = pm.step_timed(fm, min(n64, CHUNK))
-        out["fp32_storage"] = {"value": round(pts * n64 / sm, 1), "ms_per_step": round(sm * 1e3 / n64, 6),
-                               "steps": n64, "row_ms": round(rm, 6), "col_ms": round(cm, 6),
-                               "hbm_gbs_algorithmic": round(pts * n64 / sm * 32 / 1e9, 1)}
-        del pm, fm
+        out["vs_fp64_plain"] = round(value / (pts * n64 / s64), 3)
+        for mode in ("fp32_storage", "fp32_cn64" if hp == "fp32" else "fp32"):
+            pm = fcn.Plan(inst, precision=mode, **tile_kw[mode])
+            initm = pm.pack(a0.astype(np.complex64))
+            fm = initm.clone()
+            pm.step(fm, min(args.warmup, 50) or 1)
+            sm = timed_steps(pm, fm, initm, n64, torch)
+            pm.sync()
+            fm.copy_(initm)
+            rm, cm, _ = pm.step_timed(fm, min(n64, CHUNK))
+            out[mode] = {"value": round(pts * n64 / sm, 1), "ms_per_step": round(sm * 1e3 / n64, 6),
+                         "steps": n64, "row_ms": round(rm, 6), "col_ms": round(cm, 6),
+                         "hbm_gbs_algorithmic": round(pts * n64 / sm * 32 / 1e9, 1),
+                         "vs_fp64_plain": round(s64 / sm, 3)}
+            del pm, fm
 
     # ---- FP32 error against the FP64 GPU method at checkpoints; the FP64 run started from
     # the FP32-rounded input measures how much the trajectory itself amplifies FP32 rounding
@@ -522,6 +545,9 @@ def main():
         q64 = fcn.Plan(inst, precision="fp64")
         qr = fcn.Plan(inst, precision="fp64")
         qm = fcn.Plan(inst, precision="fp32_storage")
+        qc = fcn.Plan(inst, precision="fp32_cn64")
+        gc = qc.pack(a0.astype(np.complex64))
+        ok_c = True
         g32 = q32.pack(a0.astype(np.complex64))
         g64 = q64.pack(a0)
         gr = qr.pack(a0.astype(np.complex64).astype(np.complex128))
@@ -530,7 +556,7 @@ def main():
         acc = []
         done = 0
         for cp in checkpoints:
-            for q, g in ((q32, g32), (q64, g64), (qr, gr), (qm, gm)):
+            for q, g in ((q32, g32), (q64, g64), (qr, gr), (qm, gm), (qc, gc)):
                 q.step(g, cp - done)
             done = cp
             ok32 = True
@@ -544,6 +570,10 @@ def main():
                 qm.sync()
             except fcn.FcnError:
                 ok_m = False
+            try:
+                qc.sync()
+            except fcn.FcnError:
+                ok_c = False
             x64 = q64.unpack(g64)[0]
             d32 = q32.split_diag(q32.diagnostics(g32))[0]
             d64 = q64.split_diag(q64.diagnostics(g64))[0]
@@ -559,6 +589,7 @@ def main():
             else:
                 row.update(field=None, note="FP32 trajectory left the RK4 density stability region")
             row["field_fp32_storage"] = weighted_rel_err(qm.unpack(gm)[0].astype(np.complex128), x64) if ok_m else None
+            row["field_fp32_cn64"] = weighted_rel_err(qc.unpack(gc)[0].astype(np.complex128), x64) if ok_c else None
             acc.append(row)
             if not ok32:
                 break

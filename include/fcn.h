@@ -15,7 +15,7 @@
  *    instances of a plan; instance i starts at the element offset fcn_field_offset(i) and
  *    is a row-major [nr][nt] matrix with t contiguous: element (m, p) is A(r_m, t_p) with
  *    r_m = m r_max/(nr-1) and t_p = t_min + p (t_max - t_min)/nt (Sec. 3, the grid
- *    A_{m,p}).  Precision FCN_FP64 uses double2 elements, FCN_FP32 float2 elements.
+ *    A_{m,p}).  Precision FCN_FP64 uses double2 elements, the FP32 modes float2 elements.
  *    Between calls the field is in the time domain at an integer z-step.
  *  - Ownership: the caller allocates and frees every device buffer (field, workspace,
  *    diagnostics, dz log) and owns the HIP stream.  After fcn_plan_bind the library never
@@ -61,8 +61,12 @@ enum {
 /* Precision modes.  FCN_FP32_STORAGE keeps the field in FP32 (the HBM traffic of FCN_FP32)
  * and computes every stage in FP64 inside the kernels: only the two FP32 stores per step
  * round, so the error grows like a random walk instead of accumulating the FP32 transform
- * error coherently over slowly varying fields. */
-enum { FCN_FP64 = 0, FCN_FP32 = 1, FCN_FP32_STORAGE = 2 };
+ * error coherently over slowly varying fields.  FCN_FP32_CN64 removes the two largest
+ * fixed-rounding sources of FCN_FP32 at a smaller cost: FP32 field, FFTs and nonlinear step
+ * as FCN_FP32 but with every FFT twiddle carried as an FP32 hi + lo pair, and the
+ * Crank-Nicholson column solve in FP64 arithmetic (the same column kernel as
+ * FCN_FP32_STORAGE). */
+enum { FCN_FP64 = 0, FCN_FP32 = 1, FCN_FP32_STORAGE = 2, FCN_FP32_CN64 = 3 };
 
 /* One pulse and its grid. */
 typedef struct {
@@ -85,7 +89,9 @@ typedef struct {
 typedef struct {
     int32_t precision;       /* FCN_FP64; FCN_FP32 (field, FFT, CN and exponentials in FP32;
                                 density scan, operator exponents and diagnostics in FP64); or
-                                FCN_FP32_STORAGE (FP32 field, FP64 arithmetic) */
+                                FCN_FP32_STORAGE (FP32 field, FP64 arithmetic);
+                                FCN_FP32_CN64 (FP32 field and row pass with twiddle pairs,
+                                FP64 column solve) */
     int32_t adaptive;        /* 0: fixed dz per instance; 1: dz_n = clamp(max_phase/Phi, dz_min,
                                 dz_max) with Phi the peak nonlinear phase rate of A^{n-1} */
     double max_phase;        /* [rad] per step, adaptive mode */

@@ -264,7 +264,8 @@ hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int
     switch (precision) {
         case 0: return launch_col_p<double, double>(w, l, nr, a, grid, s, e0, e1);
         case 1: return launch_col_p<float, float>(w, l, nr, a, grid, s, e0, e1);
-        case 2: return launch_col_p<double, float>(w, l, nr, a, grid, s, e0, e1);
+        case 2:  // FP32 storage, FP64 arithmetic
+        case 3: return launch_col_p<double, float>(w, l, nr, a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }

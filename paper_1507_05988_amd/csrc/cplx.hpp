@@ -41,6 +41,18 @@ template <typename R>
 __device__ __forceinline__ c2<R> cmulc(c2<R> a, c2<R> b) {  // a * conj(b)
     return mk<R>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
+// a * (h + l) and a * conj(h + l) for a constant carried as a hi + lo pair (|l| <= ulp(h)/2):
+// the small product a * l is added into the fused products of a * h.
+template <typename R>
+__device__ __forceinline__ c2<R> cmul_pair(c2<R> a, c2<R> h, c2<R> l) {
+    const R px = a.x * l.x - a.y * l.y, py = a.x * l.y + a.y * l.x;
+    return mk<R>(fma(a.x, h.x, fma(-a.y, h.y, px)), fma(a.x, h.y, fma(a.y, h.x, py)));
+}
+template <typename R>
+__device__ __forceinline__ c2<R> cmulc_pair(c2<R> a, c2<R> h, c2<R> l) {
+    const R px = a.x * l.x + a.y * l.y, py = a.y * l.x - a.x * l.y;
+    return mk<R>(fma(a.x, h.x, fma(a.y, h.y, px)), fma(a.y, h.x, fma(-a.x, h.y, py)));
+}
 template <typename R>
 __device__ __forceinline__ c2<R> cscale(c2<R> a, R s) {
     return mk<R>(a.x * s, a.y * s);

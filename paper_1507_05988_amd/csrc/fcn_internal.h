@@ -79,6 +79,7 @@ enum : int {
     RK_STAGE_LEN = 64,  // stage test: NL_B uses the explicit length argument as its exponent
     RK_SCAN = 128,      // some instance of the launch has a density term: contiguous-chunk
                         // layout and the density scan (otherwise pointwise, strided layout)
+    RK_TW_PAIR = 256,   // FP32 transforms with twiddles carried as hi + lo pairs
 };
 
 // Step-length source of a row kernel.
@@ -135,6 +136,10 @@ int row_rows_per_group(int nt, int elems);
 // sweep).  With FP64 arithmetic also 16 at nt = 2048 (three radix-16 passes: 39.5 against
 // 44.2 us for the full-model row pass); FP32 keeps 8 there (25.8 against 19.4 us with 16).
 constexpr int row_elems_for(int nt, bool fp64_arith) { return nt >= 4096 || (fp64_arith && nt >= 2048) ? 16 : 8; }
+// Precision codes of include/fcn.h as seen by the two passes: FP64 arithmetic in the row pass
+// (FCN_FP64, FCN_FP32_STORAGE) and in the column pass (also FCN_FP32_CN64).
+constexpr bool row_fp64_arith(int precision) { return precision == 0 || precision == 2; }
+constexpr bool col_fp64_arith(int precision) { return precision != 1; }
 hipError_t launch_finalize(const DevInst *inst, int batch, const double *row_diag, const double *zpos,
                            const double *dz_ring, const DevState *state, double *out, hipStream_t s);
 hipError_t launch_init_state(DevState *state, unsigned long long *phi_slot, double *dz_ring, double *zpos,

@@ -124,7 +124,9 @@ struct StockhamPass {
 
     // v holds this pass's inputs: v[q*RADIX + r] = x[j + r*NT/RADIX], j = tr + q*T.
     // tw: HALF = false: W_NT^k for k < NT; HALF = true: k < NT/2 (W^(k+NT/2) = -W^k).
-    template <bool HALF>
+    // PAIR: each twiddle is hi + lo (hi the table above, lo the same-size table after it),
+    // so the transform's constants carry about twice the working precision.
+    template <bool HALF, bool PAIR>
     static __device__ __forceinline__ void run(c2<R> (&v)[E], c2<R> *lds, int tr, const c2<R> *__restrict__ tw) {
 #pragma unroll
         for (int q = 0; q < BF; q++) {
@@ -134,14 +136,19 @@ struct StockhamPass {
 #pragma unroll
                 for (int r = 1; r < RADIX; r++) {
                     const int idx = jm * r * (NT / (NS * RADIX));
-                    c2<R> w;
-                    if constexpr (HALF) {
-                        w = tw[idx & (NT / 2 - 1)];
-                        if (idx >= NT / 2) w = mk<R>(-w.x, -w.y);
+                    constexpr int TN = HALF ? NT / 2 : NT;  // entries of one table
+                    const int ti = HALF ? (idx & (NT / 2 - 1)) : idx;
+                    const bool neg = HALF && idx >= NT / 2;
+                    c2<R> w = tw[ti];
+                    if (neg) w = mk<R>(-w.x, -w.y);
+                    if constexpr (PAIR) {
+                        c2<R> wl = tw[TN + ti];
+                        if (neg) wl = mk<R>(-wl.x, -wl.y);
+                        v[q * RADIX + r] = (DIR < 0) ? cmul_pair<R>(v[q * RADIX + r], w, wl)
+                                                     : cmulc_pair<R>(v[q * RADIX + r], w, wl);
                     } else {
-                        w = tw[idx];
+                        v[q * RADIX + r] = (DIR < 0) ? cmul<R>(v[q * RADIX + r], w) : cmulc<R>(v[q * RADIX + r], w);
                     }
-                    v[q * RADIX + r] = (DIR < 0) ? cmul<R>(v[q * RADIX + r], w) : cmulc<R>(v[q * RADIX + r], w);
                 }
             }
             SmallDFT<R, RADIX, DIR>::run(&v[q * RADIX]);
@@ -171,18 +178,19 @@ struct StockhamPass {
 #pragma unroll
                 for (int r = 0; r < Next::RADIX; r++)
                     v[q * Next::RADIX + r] = lds[lpad(tr + q * T + r * (NT / Next::RADIX))];
-            Next::template run<HALF>(v, lds, tr, tw);
+            Next::template run<HALF, PAIR>(v, lds, tr, tw);
         }
     }
 };
 
 // Full transform, strided layout in and out.  DIR = -1 forward, +1 inverse (unscaled).
-// HALF: tw holds the first NT/2 table entries only.  Every thread of the workgroup must
-// call it (it contains barriers).
-template <typename R, int NT, int E, int DIR, bool HALF = false>
+// HALF: tw holds the first NT/2 table entries only.  PAIR: tw is followed by a table of the
+// same size holding the low parts of the twiddles.  Every thread of the workgroup must call
+// it (it contains barriers).
+template <typename R, int NT, int E, int DIR, bool HALF = false, bool PAIR = false>
 __device__ __forceinline__ void row_fft(c2<R> (&v)[E], c2<R> *lds, int tr, const c2<R> *__restrict__ tw) {
     static_assert(NT >= E && (NT & (NT - 1)) == 0, "NT must be a power of two >= E");
-    StockhamPass<R, NT, E, DIR, 1>::template run<HALF>(v, lds, tr, tw);
+    StockhamPass<R, NT, E, DIR, 1>::template run<HALF, PAIR>(v, lds, tr, tw);
 }
 
 }  // namespace fcn

@@ -81,7 +81,7 @@ fcn_status fcn_parareal(fcn_plan_t fine, fcn_plan_t coarse, fcn_net_t net, const
     if (workspace_bytes < L.total) return FCN_E_SIZE;
     if (!plan_bound(fine) || !plan_bound(coarse) || (fine_serial && !plan_bound(fine_serial))) return FCN_E_STATE;
     // complex64 fields only (FP32 or FP32 storage), one stream for everything
-    auto c64 = [](fcn_plan_t p) { return plan_precision(p) == FCN_FP32 || plan_precision(p) == FCN_FP32_STORAGE; };
+    auto c64 = [](fcn_plan_t p) { return plan_precision(p) != FCN_FP64; };
     if (!c64(fine) || !c64(coarse) || (fine_serial && !c64(fine_serial))) return FCN_E_UNSUPPORTED;
     hipStream_t st = plan_stream(fine);
     if (plan_stream(coarse) != st || (fine_serial && plan_stream(fine_serial) != st) || (net && net_stream(net) != st))

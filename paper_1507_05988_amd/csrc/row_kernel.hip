@@ -360,10 +360,14 @@ struct RowCfg {
     static constexpr int RPW = T >= 256 ? 1 : 256 / T;
     static constexpr int THREADS = T * RPW;
     static constexpr int LROW = NT + NT / 32;
-    // FP32: the first half of the twiddle table is staged in LDS (FP64 kernels keep the
-    // global table: the extra LDS and addressing push them into register spills)
-    static constexpr bool TW_LDS = sizeof(c2<R>) == 8 && sizeof(c2<R>) * (size_t)(RPW * LROW + NT / 2) <= 150 * 1024;
-    static constexpr int TWN = TW_LDS ? NT / 2 : 1;
+    // FP32: the first half of the twiddle table (and of its low parts with RK_TW_PAIR) is
+    // staged in LDS (FP64 kernels keep the global table: the extra LDS and addressing push
+    // them into register spills)
+    static constexpr bool PAIR = (FLAGS & RK_TW_PAIR) != 0;
+    static constexpr int TWH = PAIR ? NT : NT / 2;
+    static constexpr bool TW_LDS = sizeof(c2<R>) == 8 && sizeof(c2<R>) * (size_t)(RPW * LROW + TWH) <= 150 * 1024;
+    static constexpr int TWN = TW_LDS ? TWH : 1;
+    static_assert(!PAIR || sizeof(R) == 4, "twiddle pairs are for FP32 arithmetic");
 };
 
 // R: arithmetic precision; ST: storage precision of the field (ST = float with R = double is
@@ -415,13 +419,16 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 
     const c2<R> *twp = tw;
     if constexpr (FFTS && Cfg::TW_LDS) {
-        for (int i = tid; i < NT / 2; i += Cfg::THREADS) twl[i] = tw[i];
+        for (int i = tid; i < NT / 2; i += Cfg::THREADS) {
+            twl[i] = tw[i];
+            if constexpr (Cfg::PAIR) twl[NT / 2 + i] = tw[NT + i];  // low parts: table of NT after the NT highs
+        }
         __syncthreads();
         twp = twl;
     }
 
     if constexpr ((FLAGS & RK_IFFT_IN) != 0) {
-        row_fft<R, NT, E, +1, Cfg::TW_LDS>(v, row_lds, tr, twp);
+        row_fft<R, NT, E, +1, Cfg::TW_LDS, Cfg::PAIR>(v, row_lds, tr, twp);
         const R sc = R(1.0 / NT);
 #pragma unroll
         for (int k = 0; k < E; k++) v[k] = cscale<R>(v[k], sc);
@@ -480,7 +487,7 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
         }
     }
 
-    if constexpr ((FLAGS & RK_FFT_OUT) != 0) row_fft<R, NT, E, -1, Cfg::TW_LDS>(v, row_lds, tr, twp);
+    if constexpr ((FLAGS & RK_FFT_OUT) != 0) row_fft<R, NT, E, -1, Cfg::TW_LDS, Cfg::PAIR>(v, row_lds, tr, twp);
 
     if constexpr ((FLAGS & RK_STORE) != 0) {
         if (active) {
@@ -538,22 +545,23 @@ constexpr int RK_T_FFT = RK_FFT_OUT | RK_STORE;
 constexpr int RK_T_IFFT = RK_IFFT_IN | RK_STORE;
 constexpr int RK_T_NL = RK_NL_B | RK_STORE | RK_STAGE_LEN;
 
-template <typename R, typename ST>
+// X: flags added to every combination at compile time (RK_TW_PAIR for FP32 with twiddle pairs)
+template <typename R, typename ST, int X = 0>
 static hipError_t launch_row_p(int nt, int flags, const RowArgs &a, int grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1) {
     switch (flags) {
-        case RK_FIRST: return launch_row_nt<R, ST, RK_FIRST>(nt, a, grid, s, e0, e1);
-        case RK_MIDDLE: return launch_row_nt<R, ST, RK_MIDDLE>(nt, a, grid, s, e0, e1);
-        case RK_LAST: return launch_row_nt<R, ST, RK_LAST>(nt, a, grid, s, e0, e1);
-        case RK_DIAG_ONLY: return launch_row_nt<R, ST, RK_DIAG_ONLY>(nt, a, grid, s, e0, e1);
-        case RK_T_NL: return launch_row_nt<R, ST, RK_T_NL>(nt, a, grid, s, e0, e1);
-        case RK_FIRST | RK_SCAN: return launch_row_nt<R, ST, RK_FIRST | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_MIDDLE | RK_SCAN: return launch_row_nt<R, ST, RK_MIDDLE | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_LAST | RK_SCAN: return launch_row_nt<R, ST, RK_LAST | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_DIAG_ONLY | RK_SCAN: return launch_row_nt<R, ST, RK_DIAG_ONLY | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_T_NL | RK_SCAN: return launch_row_nt<R, ST, RK_T_NL | RK_SCAN>(nt, a, grid, s, e0, e1);
-        case RK_T_FFT: return launch_row_nt<R, ST, RK_T_FFT>(nt, a, grid, s, e0, e1);
-        case RK_T_IFFT: return launch_row_nt<R, ST, RK_T_IFFT>(nt, a, grid, s, e0, e1);
+        case RK_FIRST: return launch_row_nt<R, ST, (RK_FIRST) | X>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE: return launch_row_nt<R, ST, (RK_MIDDLE) | X>(nt, a, grid, s, e0, e1);
+        case RK_LAST: return launch_row_nt<R, ST, (RK_LAST) | X>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY: return launch_row_nt<R, ST, (RK_DIAG_ONLY) | X>(nt, a, grid, s, e0, e1);
+        case RK_T_NL: return launch_row_nt<R, ST, (RK_T_NL) | X>(nt, a, grid, s, e0, e1);
+        case RK_FIRST | RK_SCAN: return launch_row_nt<R, ST, (RK_FIRST | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE | RK_SCAN: return launch_row_nt<R, ST, (RK_MIDDLE | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
+        case RK_LAST | RK_SCAN: return launch_row_nt<R, ST, (RK_LAST | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY | RK_SCAN: return launch_row_nt<R, ST, (RK_DIAG_ONLY | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
+        case RK_T_NL | RK_SCAN: return launch_row_nt<R, ST, (RK_T_NL | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
+        case RK_T_FFT: return launch_row_nt<R, ST, (RK_T_FFT) | X>(nt, a, grid, s, e0, e1);
+        case RK_T_IFFT: return launch_row_nt<R, ST, (RK_T_IFFT) | X>(nt, a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -565,11 +573,12 @@ int row_rows_per_group(int nt, int elems) {
 
 hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1) {
-    if (elems != row_elems_for(nt, precision != 1)) return hipErrorInvalidValue;
+    if (elems != row_elems_for(nt, row_fp64_arith(precision))) return hipErrorInvalidValue;
     switch (precision) {
         case 0: return launch_row_p<double, double>(nt, flags, a, grid, s, e0, e1);
         case 1: return launch_row_p<float, float>(nt, flags, a, grid, s, e0, e1);
         case 2: return launch_row_p<double, float>(nt, flags, a, grid, s, e0, e1);
+        case 3: return launch_row_p<float, float, RK_TW_PAIR>(nt, flags, a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }

@@ -216,16 +216,18 @@ void choose_col_tiles(int precision, int nr, const fcn_options &opt, int &w, int
 
 fcn_status build_plan(fcn_plan_t p) {
     const int B = p->batch;
-    p->csize = p->precision == FCN_FP32 ? 8 : 16;
+    const bool row64 = row_fp64_arith(p->precision);
+    const bool pair = p->precision == FCN_FP32_CN64;
+    p->csize = row64 ? 16 : 8;
     p->dinst.resize(B);
 
-    // twiddle tables per distinct nt
+    // twiddle tables per distinct nt (with twiddle pairs: nt high parts, then nt low parts)
     std::map<int, int> tw_off;
     size_t tw_elems = 0;
     for (const auto &in : p->insts)
         if (!tw_off.count(in.nt)) {
             tw_off[in.nt] = (int)tw_elems;
-            tw_elems += in.nt;
+            tw_elems += pair ? 2 * (size_t)in.nt : in.nt;
         }
     p->twiddles.assign(tw_elems * p->csize, 0);
     for (auto &kv : tw_off) {
@@ -233,9 +235,15 @@ fcn_status build_plan(fcn_plan_t p) {
         twiddle_table(kv.first, re, im);
         for (int k = 0; k < kv.first; k++) {
             const size_t e = (size_t)kv.second + k;
-            if (p->precision != FCN_FP32) {
+            if (row64) {
                 double v[2] = {re[k], im[k]};
                 memcpy(&p->twiddles[e * 16], v, 16);
+            } else if (pair) {
+                // W = hi + lo to about 2^-48: hi the nearest float pair, lo the rounded rest
+                const float hi[2] = {(float)re[k], (float)im[k]};
+                const float lo[2] = {(float)(re[k] - (double)hi[0]), (float)(im[k] - (double)hi[1])};
+                memcpy(&p->twiddles[e * 8], hi, 8);
+                memcpy(&p->twiddles[(e + kv.first) * 8], lo, 8);
             } else {
                 float v[2];
                 round_unit_f32(re[k], im[k], v);
@@ -334,7 +342,7 @@ fcn_status build_plan(fcn_plan_t p) {
         b.scan = 0;
         for (int i : kv.second)
             if (p->dinst[i].need_rho != 0.0) b.scan = RK_SCAN;
-        const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt, p->precision != FCN_FP32));
+        const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)));
         b.grid = (b.nitems + rpw - 1) / rpw;
         p->row_buckets.push_back(b);
     }
@@ -445,7 +453,7 @@ hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, in
         a.seed_slots = seed;
         a.stage_len = stage_len;
         const bool nl = (flags & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
-        hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt, p->precision != FCN_FP32), nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
+        hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)), nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
                                   bi == 0 ? e0 : nullptr, bi + 1 == nb ? e1 : nullptr);
         if (e != hipSuccess) return e;
     }
@@ -596,7 +604,8 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
     p->insts.assign(inst, inst + batch);
     if (opt) p->opt = *opt;
     p->precision = p->opt.precision;
-    if (p->precision != FCN_FP64 && p->precision != FCN_FP32 && p->precision != FCN_FP32_STORAGE) {
+    if (p->precision != FCN_FP64 && p->precision != FCN_FP32 && p->precision != FCN_FP32_STORAGE &&
+        p->precision != FCN_FP32_CN64) {
         delete p;
         return FCN_E_ARG;
     }
@@ -671,7 +680,7 @@ fcn_status fcn_plan_tiles(fcn_plan_t p, int32_t *col_tile, int32_t *col_rows, in
     if (row_elems) {
         int nt_max = 0;
         for (const auto &in : p->insts) nt_max = std::max(nt_max, (int)in.nt);
-        *row_elems = row_elems_for(nt_max, p->precision != FCN_FP32);
+        *row_elems = row_elems_for(nt_max, row_fp64_arith(p->precision));
     }
     return FCN_OK;
 }

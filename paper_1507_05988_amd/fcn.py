@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcn.so")
 
 FCN_OK, FCN_E_ARG, FCN_E_SIZE, FCN_E_HIP, FCN_E_NONFINITE, FCN_E_STATE, FCN_E_UNSUPPORTED = range(7)
-FCN_FP64, FCN_FP32, FCN_FP32_STORAGE = 0, 1, 2
-PRECISIONS = {"fp64": FCN_FP64, "fp32": FCN_FP32, "fp32_storage": FCN_FP32_STORAGE}
+FCN_FP64, FCN_FP32, FCN_FP32_STORAGE, FCN_FP32_CN64 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FCN_FP64, "fp32": FCN_FP32, "fp32_storage": FCN_FP32_STORAGE, "fp32_cn64": FCN_FP32_CN64}
 STAGE_FFT, STAGE_IFFT, STAGE_CN, STAGE_NL = 0, 1, 2, 3
 DIAG_SCALARS = 8
 DIAG_NAMES = ("energy", "i_max", "i_axis", "rho_max", "phi", "z", "step", "dz_prev")
@@ -147,8 +147,9 @@ def make_instance(inst: dict) -> Instance:
 class Plan:
     """A batch of pulses stepped together on one GPU.
 
-    instances: list of instance dicts (see workloads.py); precision "fp64", "fp32" or
-    "fp32_storage" (FP32 field, FP64 arithmetic in the kernels).
+    instances: list of instance dicts (see workloads.py); precision "fp64", "fp32",
+    "fp32_storage" (FP32 field, FP64 arithmetic in the kernels) or "fp32_cn64" (FP32 field and
+    row pass with twiddles as hi + lo pairs, FP64-arithmetic column solve).
     The field is one flat complex torch tensor on the device (complex128 for fp64, else complex64),
     instance i occupying [offset(i), offset(i) + nr*nt) as a row-major [nr][nt] matrix.
     """

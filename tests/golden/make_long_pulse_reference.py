@@ -5,9 +5,10 @@ fluence at every 16th radius and the field at 25 fixed grid points.  It calls on
 (and the seeded input builders), so every stored value is the oracle's.
 
 Run: python tests/golden/make_long_pulse_reference.py [--max-steps N]   (about 90 minutes on
-8 cores for the 10000-step checkpoint; the file is rewritten after each checkpoint, so a
-shorter run keeps the earlier ones).  Rewrite only with a commit that names the passage or
-reading of the paper that changed the oracle's arithmetic."""
+8 cores for the 10000-step checkpoint; the file is rewritten after each checkpoint, and a
+later run of the same oracle source computes only the checkpoints still missing).  Rewrite
+only with a commit that names the passage or reading of the paper that changed the oracle's
+arithmetic."""
 import argparse
 import hashlib
 import json
@@ -68,10 +69,19 @@ def main():
                      "independent runs from z = 0",
             "oracle_source_sha256": hashlib.sha256(oracle.source().encode()).hexdigest(),
             "checkpoints": []}
+    if os.path.exists(OUT):  # keep the checkpoints an earlier run of the same oracle source wrote
+        with open(OUT) as fh:
+            old = json.load(fh)
+        if old.get("oracle_source_sha256") == data["oracle_source_sha256"]:
+            data["checkpoints"] = [c for c in old["checkpoints"] if c["steps"] in CHECKPOINTS]
+    have = {c["steps"] for c in data["checkpoints"]}
     for n in CHECKPOINTS:
         if n > args.max_steps:
             break
+        if n in have:
+            continue
         data["checkpoints"].append(checkpoint(inst, a0, n))
+        data["checkpoints"].sort(key=lambda c: c["steps"])
         with open(OUT, "w") as fh:
             json.dump(data, fh, indent=1)
             fh.write("\n")

@@ -4,7 +4,8 @@ Each workload runs at its real grid (and batch) with the plan options bench.py u
 oracle follows the same steps on the whole field where that takes seconds, else on sampled
 instances of a batch (each instance of a batch is bit-identical to the instance run alone,
 tested separately, so a sampled instance checks the batched launch).  Tolerances: FP64 1e-10;
-FP32 the per-step bound 1e-6 accumulated over the steps; FP32 storage 1e-6 over <= 100 steps.
+FP32 and FP32-CN64 the per-step bound 1e-6 accumulated over the steps; FP32 storage 1e-6 over
+<= 100 steps.
 """
 import math
 import sys
@@ -40,7 +41,8 @@ def _run(insts, precision, nsteps, fields, **kw):
     return plan.unpack(f)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 60 * 1e-6), ("fp32_storage", 1e-6)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 60 * 1e-6), ("fp32_storage", 1e-6),
+                                           ("fp32_cn64", 60 * 1e-6)])
 def test_full_model_pulse_full_size(precision, tol):
     """Full-model pulse, 512 x 2048, 60 steps of 5 mm from z = 0 (the bench workload)."""
     inst = wl.config_full()

@@ -448,6 +448,82 @@ def test_fp32_storage_batch_and_graph():
         assert np.array_equal(got[i], single)
 
 
+# ------------------------------- FP32 row pass with twiddle pairs, FP64-arithmetic column solve
+
+def _rms(a, ref):
+    return float(np.sqrt(np.mean(np.abs(a - ref) ** 2) / np.mean(np.abs(ref) ** 2)))
+
+
+@pytest.mark.parametrize("nt", [64, 256, 2048, 8192])
+def test_fp32_cn64_stages(nt):
+    """FFT and inverse FFT with twiddles as hi + lo pairs: within the FP32 arithmetic bound and,
+    on the RMS over the grid, no less accurate than the plain FP32 transforms (whose rounded
+    twiddles add a fixed error); the column solve is the FP32-storage kernel, bitwise."""
+    say(f"fp32-cn64 stages nt={nt}")
+    nr = 37
+    inst = wl.config_full(nr=nr, nt=nt)
+    a = wl.random_field(nr, nt, seed=nt + 2)
+    a32 = a.astype(np.complex64).astype(np.complex128)
+    pc = _plan(inst, "fp32_cn64")
+    p32 = _plan(inst, "fp32")
+    tol = 3e-7 * math.log2(nt)
+    for stage, want in ((fcn.STAGE_FFT, oracle.fft_rows(a32)), (fcn.STAGE_IFFT, oracle.fft_rows(a32, inverse=True))):
+        got = {}
+        for name, p in (("cn64", pc), ("fp32", p32)):
+            f = p.pack(a)
+            p.stage(stage, f)
+            got[name] = p.unpack(f)[0].astype(np.complex128)
+        e = relmax(got["cn64"], want)
+        r_pair, r_plain = _rms(got["cn64"], want), _rms(got["fp32"], want)
+        say(f"  stage {stage}: max {e:.2e}, rms {r_pair:.2e} (plain FP32 twiddles {r_plain:.2e})")
+        assert e < tol
+        assert r_pair <= r_plain * 1.05
+    ps = _plan(inst, "fp32_storage")
+    f, g = pc.pack(a), ps.pack(a)
+    pc.stage(fcn.STAGE_CN, f, 0.05)
+    ps.stage(fcn.STAGE_CN, g, 0.05)
+    got_c, got_s = pc.unpack(f)[0], ps.unpack(g)[0]
+    assert np.array_equal(got_c, got_s)
+    assert relmax(got_c.astype(np.complex128), oracle.cn_columns(inst, a32, 0.05)) < 2.0 ** -23
+    pc.sync()
+
+
+def test_fp32_cn64_run_errors_vs_fp64():
+    """Full-model pulse on a 128 x 512 grid, 300 steps, and the Kerr trajectory of the FP32-
+    storage test, 800 steps, against the FP64 GPU method: FP32-CN64 sits between FP32 and
+    FP32 storage, well below FP32."""
+    cases = ((wl.config_full(nr=128, nt=512), 300), (wl.config_parareal_trajectory(5000, nr=128, nt=512), 800))
+    for inst, n in cases:
+        a0 = wl.gaussian_field(inst)
+        ref, _ = _run(inst, "fp64", n, a0=a0)
+        e = {}
+        for mode in ("fp32", "fp32_cn64", "fp32_storage"):
+            got, _ = _run(inst, mode, n, a0=a0.astype(np.complex64))
+            e[mode] = werr(got.astype(np.complex128), ref)
+        say(f"  {inst['nr']}x{inst['nt']}, {n} steps vs FP64: " + ", ".join(f"{k} {v:.2e}" for k, v in e.items()))
+        assert e["fp32_cn64"] < e["fp32"] / 2
+        assert e["fp32_storage"] < e["fp32_cn64"]
+        assert e["fp32_cn64"] < n * 1e-6
+
+
+def test_fp32_cn64_batch_and_graph():
+    """The ragged batch and the graph replay in FP32-CN64 mode give the same bits as single
+    instances stepped eagerly (instances with and without a density term)."""
+    import torch
+    insts = [wl.config_small(nr=40, nt=256), wl.config_full(nr=72, nt=512)]
+    fields = [wl.gaussian_field(i, np.complex64) for i in insts]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch = _plan(insts, "fp32_cn64", use_graph=True, stream=stream)
+        f = batch.pack(fields)
+        batch.step(f, 37)  # 2 graph replays of 16 steps + eager remainder
+        batch.sync()
+        got = batch.unpack(f)
+    for i, inst in enumerate(insts):
+        single, _ = _run(inst, "fp32_cn64", 37, a0=fields[i])
+        assert np.array_equal(got[i], single)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 10 * 1e-6)])
 def test_paper_grid_nr_2112(precision, tol):
     """The radial size of the paper's timing example (Nr = 2112, Table 2): tall columns solved

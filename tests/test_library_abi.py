@@ -100,7 +100,29 @@ def test_fp32_storage_mode_on_host(lib):
         sizes[prec] = sz.value
         lib.fcn_plan_destroy(h)
     assert sizes[fcn.FCN_FP32_STORAGE] >= sizes[fcn.FCN_FP32] + 8 * (256 + 512)
-    assert _create(lib, insts, precision=3)[0] == fcn.FCN_E_ARG
+    assert _create(lib, insts, precision=4)[0] == fcn.FCN_E_ARG
+
+
+def test_fp32_cn64_mode_on_host(lib):
+    """FCN_FP32_CN64 plans: the FP32 field size, and twiddle tables twice the FP32 ones (the
+    low parts follow the high parts)."""
+    insts = [wl.config_small(nr=64, nt=256), wl.config_small(nr=40, nt=512)]
+    sizes = {}
+    for prec in (fcn.FCN_FP32, fcn.FCN_FP32_CN64):
+        rc, h = _create(lib, insts, precision=prec)
+        assert rc == fcn.FCN_OK
+        sz = ctypes.c_size_t()
+        assert lib.fcn_field_size(h, ctypes.byref(sz)) == 0
+        assert sz.value == 64 * 256 + 40 * 512
+        assert lib.fcn_plan_workspace_size(h, ctypes.byref(sz)) == 0
+        sizes[prec] = sz.value
+        w, l, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert lib.fcn_plan_tiles(h, ctypes.byref(w), ctypes.byref(l), ctypes.byref(e)) == 0
+        assert e.value == 8  # FP32 row arithmetic
+        if prec == fcn.FCN_FP32_CN64:
+            assert l.value == 8  # the FP64-arithmetic column solve keeps 8 rows per thread
+        lib.fcn_plan_destroy(h)
+    assert sizes[fcn.FCN_FP32_CN64] >= sizes[fcn.FCN_FP32] + 8 * (256 + 512)
 
 
 def test_invalid_options_rejected(lib):

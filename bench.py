@@ -15,7 +15,8 @@ arithmetic) and the FP32-CN64 mode (FP32 row pass with twiddle pairs, FP64 colum
 the same workload, the errors of the three FP32-field modes against FP64 at
 checkpoints (with the FP64 run's own sensitivity to FP32 input rounding as the
 conditioning floor), parareal along z on a held-out learned-coarse trajectory (classical
-and learned coarse propagator, against the serial FP64 plain method), the long-distance
+and learned coarse propagator, fine steps in FP32-CN64 and in FP32 storage, against the
+serial FP64 plain method), the long-distance
 pulse (1024 x 8192, adaptive dz) at checkpoints up to 10^4 steps (FP32 modes against FP64,
 FP64 against the CPU oracle's stored values; --long-pulse-checkpoints extends it), the
 roofline of the dominant kernel and the CPU oracle's rate on the host.
@@ -323,9 +324,9 @@ def coarse_net_measurement(torch):
     return out
 
 
-def parareal_measurement(torch):
+def parareal_measurement(torch, precision="fp32_cn64"):
     """Parareal along z for held-out learned-coarse trajectory 2000 (Nr=512, Nt=2048, Kerr only,
-    never used in training), fine and coarse FCN steps in FP32 storage, against the serial
+    never used in training), fine and coarse FCN steps in `precision`, against the serial
     FP64 plain method over the same steps (device time):
       * the parareal workload as specified, 32 windows x 50 steps of 0.2 mm, classical coarse
         step (one FCN step per window);
@@ -343,7 +344,7 @@ def parareal_measurement(torch):
     pts = int(inst["nr"]) * int(inst["nt"])
     wfile = os.path.join(ROOT, "paper_1507_05988_amd", "weights", "coarse_c32_bf16.npz")
     net = coarse.CoarseNet.load(wfile) if os.path.exists(wfile) else None
-    res = {"trajectory": 2000, "grid": "512x2048", "fine_precision": "fp32_storage", "tol": 1e-4}
+    res = {"trajectory": 2000, "grid": "512x2048", "fine_precision": precision, "tol": 1e-4}
     for label, nwin, spw, learned in (("windows_32x50", wl.PARAREAL_WINDOWS, wl.PARAREAL_STEPS_PER_WINDOW, False),
                                       ("windows_8x250", wl.LEARNED_WINDOWS, wl.LEARNED_STEPS_PER_WINDOW, True)):
         work = pts * nwin * spw
@@ -367,7 +368,7 @@ def parareal_measurement(torch):
         if learned and net is not None:
             variants.append(("learned", net))
         for name, m in variants:
-            kw = dict(windows=nwin, steps_per_window=spw, kmax=nwin, tol=1e-4, precision="fp32_storage",
+            kw = dict(windows=nwin, steps_per_window=spw, kmax=nwin, tol=1e-4, precision=precision,
                       fallback=True)
             if m is not None:
                 kw.update(channels=m["channels"], bf16=m["bf16"], kappa=m["kappa"], s_ref=m["s_ref"])
@@ -602,7 +603,9 @@ def main():
     if not args.no_long_pulse:
         out["long_pulse"] = long_pulse_measurement(torch, [int(x) for x in args.long_pulse_checkpoints.split(",")])
     if not args.no_parareal:
-        out["parareal"] = parareal_measurement(torch)
+        # fine and coarse steps in FP32-CN64 (parareal target 1e-4), and in FP32 storage (1e-5)
+        out["parareal"] = parareal_measurement(torch, "fp32_cn64")
+        out["parareal_fp32_storage"] = parareal_measurement(torch, "fp32_storage")
     if not args.no_net:
         out["coarse_net"] = coarse_net_measurement(torch)
 

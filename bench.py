@@ -116,32 +116,56 @@ def cpu_baseline(inst, a0, seconds: float):
 
 def batched_sweep_measurement(torch):
     """The 64-pulse ragged sweep (Nr in {256, 512, 1024}, Nt in {512 ... 4096}, about 7.5e7
-    points, Kerr, one FP32 plan with autotuned column tiles), 100 steps: aggregate throughput
-    and per-pass kernel times (kernel-own events; one launch per distinct Nt or Nr)."""
+    points, Kerr, one plan with autotuned column tiles), 100 steps, in FP64, FP32 and
+    FP32-CN64: aggregate throughput, per-pass kernel times (kernel-own events; one launch per
+    distinct Nt or Nr) and the largest per-instance field error against the FP64 GPU run."""
     from paper_1507_05988_amd import autotune, fcn
     from paper_1507_05988_amd import workloads as wl
 
     insts = wl.config_batch()
     pts = sum(int(i["nr"]) * int(i["nt"]) for i in insts)
-    t = autotune.tune(insts, "fp32", steps=10, repeats=2)
-    plan = fcn.Plan(insts, precision="fp32", col_tile=t["col_tile"], col_rows=t["col_rows"])
-    init = plan.pack([wl.gaussian_field(i, np.complex64) for i in insts])
-    f = init.clone()
-    plan.step(f, 5)
-    sec = timed_steps(plan, f, init, wl.BATCH_STEPS, torch)
-    f.copy_(init)
-    krow, kcol, _ = plan.step_timed(f, 20)
-    plan.sync()
-    value = pts * wl.BATCH_STEPS / sec
     byt = pts * 16
-    return {"points": pts, "instances": len(insts), "steps": wl.BATCH_STEPS, "value": round(value, 1),
-            "unit": "grid-pt z-steps/s", "ms_per_step": round(sec * 1e3 / wl.BATCH_STEPS, 4),
+    t64 = autotune.tune(insts, "fp64", steps=10, repeats=2)
+    p64 = fcn.Plan(insts, precision="fp64", col_tile=t64["col_tile"], col_rows=t64["col_rows"])
+    init64 = p64.pack([wl.gaussian_field(i) for i in insts])
+    f64 = init64.clone()
+    p64.step(f64, 5)
+    sec64 = timed_steps(p64, f64, init64, wl.BATCH_STEPS, torch)
+    f64.copy_(init64)
+    p64.step(f64, wl.BATCH_STEPS)
+    p64.sync()
+    ref = p64.unpack(f64)
+    del p64, f64, init64
+    out = {"points": pts, "instances": len(insts), "steps": wl.BATCH_STEPS, "unit": "grid-pt z-steps/s",
+           "fp64_plain": {"value": round(pts * wl.BATCH_STEPS / sec64, 1),
+                          "ms_per_step": round(sec64 * 1e3 / wl.BATCH_STEPS, 4),
+                          "col_tile": [t64["col_tile"], t64["col_rows"]]}}
+    for prec in ("fp32", "fp32_cn64"):
+        t = autotune.tune(insts, prec, steps=10, repeats=2)
+        plan = fcn.Plan(insts, precision=prec, col_tile=t["col_tile"], col_rows=t["col_rows"])
+        init = plan.pack([wl.gaussian_field(i, np.complex64) for i in insts])
+        f = init.clone()
+        plan.step(f, 5)
+        sec = timed_steps(plan, f, init, wl.BATCH_STEPS, torch)
+        f.copy_(init)
+        krow, kcol, _ = plan.step_timed(f, 20)
+        f.copy_(init)
+        plan.step(f, wl.BATCH_STEPS)
+        plan.sync()
+        errs = [weighted_rel_err(g.astype(np.complex128), r) for g, r in zip(plan.unpack(f), ref)]
+        value = pts * wl.BATCH_STEPS / sec
+        out[prec] = {
+            "value": round(value, 1), "ms_per_step": round(sec * 1e3 / wl.BATCH_STEPS, 4),
             "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1), "row_pass_ms": round(krow, 4),
             "col_pass_ms": round(kcol, 4), "col_tile": [t["col_tile"], t["col_rows"]],
+            "field_error_vs_fp64_max": max(errs), "field_error_vs_fp64_median": float(np.median(errs)),
+            "vs_fp64_plain": round(sec64 / sec, 3),
             "roofline_row_pass": {"bound": "hbm", "achieved": round(byt / (krow * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                                   "unit": "GB/s", "frac": round(byt / (krow * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "roofline_col_pass": {"bound": "hbm", "achieved": round(byt / (kcol * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                                   "unit": "GB/s", "frac": round(byt / (kcol * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+        del plan, f, init
+    return out
 
 
 def paper_shapes_measurement(torch):

@@ -37,6 +37,26 @@ struct Eq {  // lower, upper, rhs of one normalised (unit diagonal) reduced equa
     c2<R> l, u, r;
 };
 
+// 1 / z for the pivots of the elimination.  They depend on the operator only, never on the
+// field, and |z|^2 stays of order one (the matrix has Hermitian part I after the diagonal
+// similarity above), so the hardware reciprocal refined by Newton-Raphson steps
+// r <- r + r (1 - d r) replaces the IEEE division sequence: two steps from the
+// reciprocal's estimate reach the FP64 rounding level, one step the FP32 level.
+template <typename R>
+__device__ __forceinline__ c2<R> pivot_rcp(c2<R> z) {
+    const R d = z.x * z.x + z.y * z.y;
+    R r;
+    if constexpr (sizeof(R) == 8) {
+        r = __builtin_amdgcn_rcp(d);
+        r = fma(r, fma(-d, r, 1.0), r);
+        r = fma(r, fma(-d, r, 1.0), r);
+    } else {
+        r = __builtin_amdgcn_rcpf(d);
+        r = fmaf(r, fmaf(-d, r, 1.0f), r);
+    }
+    return mk<R>(z.x * r, -z.y * r);
+}
+
 // R: arithmetic precision; ST: storage precision of the spectrum (see the row kernel).
 template <typename R, typename ST, int W, int L>
 __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
@@ -126,7 +146,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     {
         R lr, bi, ur;
         row_coef(1, lr, bi, ur);
-        c2<R> ip = crcp<R>(mk<R>(R(1), bi));
+        c2<R> ip = pivot_rcp<R>(mk<R>(R(1), bi));
         mu[1] = cmul<R>(mk<R>(R(0), ur), ip);
         rp[1] = cmul<R>(rhs_of(1, lr, bi, ur), ip);
         sp[1] = cmul<R>(mk<R>(R(0), lr), ip);
@@ -135,7 +155,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
             row_coef(i, lr, bi, ur);
             // pivot b_i - l_i mu_{i-1}
             const c2<R> lmu = cmul_i<R>(mu[i - 1], lr);
-            ip = crcp<R>(mk<R>(R(1) - lmu.x, bi - lmu.y));
+            ip = pivot_rcp<R>(mk<R>(R(1) - lmu.x, bi - lmu.y));
             mu[i] = cmul<R>(mk<R>(R(0), ur), ip);
             rp[i] = cmul<R>(csub<R>(rhs_of(i, lr, bi, ur), cmul_i<R>(rp[i - 1], lr)), ip);
             sp[i] = cmul<R>(cmul_i<R>(sp[i - 1], -lr), ip);
@@ -160,7 +180,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     {
         const c2<R> u0 = mk<R>(R(0), ur0);
         const c2<R> uA = cmul<R>(u0, A);
-        const c2<R> idg = crcp<R>(mk<R>(R(1) - uA.x, bi0 - uA.y));
+        const c2<R> idg = pivot_rcp<R>(mk<R>(R(1) - uA.x, bi0 - uA.y));
         e0.l = cmul<R>(mk<R>(R(0), lr0), idg);
         const c2<R> uC = cmul<R>(u0, C);
         e0.u = cmul<R>(mk<R>(-uC.x, -uC.y), idg);
@@ -168,7 +188,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
 
         const c2<R> lL = mk<R>(R(0), lrL);
         const c2<R> lC = cmul<R>(lL, Cl);
-        const c2<R> idg1 = crcp<R>(mk<R>(R(1) - lC.x, biL - lC.y));
+        const c2<R> idg1 = pivot_rcp<R>(mk<R>(R(1) - lC.x, biL - lC.y));
         const c2<R> lA = cmul<R>(lL, Al);
         e1.l = cmul<R>(mk<R>(-lA.x, -lA.y), idg1);
         e1.u = cmul<R>(mk<R>(R(0), urL), idg1);
@@ -191,7 +211,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
             if (i + h < nred) hi = myred[i + h]; else hi = Eq<R>{czero<R>(), czero<R>(), czero<R>()};
             // eq_i - l_i eq_{i-h} - u_i eq_{i+h}, then renormalise
             const c2<R> dg = csub<R>(csub<R>(mk<R>(R(1), R(0)), cmul<R>(me.l, lo.u)), cmul<R>(me.u, hi.l));
-            const c2<R> idg = crcp<R>(dg);
+            const c2<R> idg = pivot_rcp<R>(dg);
             const c2<R> nl = cmul<R>(cmul<R>(me.l, lo.l), idg);
             const c2<R> nu = cmul<R>(cmul<R>(me.u, hi.u), idg);
             const c2<R> nrh = cmul<R>(csub<R>(csub<R>(me.r, cmul<R>(me.l, lo.r)), cmul<R>(me.u, hi.r)), idg);

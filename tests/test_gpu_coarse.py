@@ -289,15 +289,16 @@ def test_parareal_falls_back_on_corrupted_network_weights():
         assert torch.equal(U[j + 1], ref[j])
 
 
-@pytest.mark.parametrize("learned", [False, True])
-def test_native_parareal_driver_matches_python_driver(learned):
+@pytest.mark.parametrize("learned,precision", [(False, "fp32_storage"), (True, "fp32_storage"),
+                                                (True, "fp32_cn64")])
+def test_native_parareal_driver_matches_python_driver(learned, precision):
     """fcn_parareal (the library's driver) and the Python driver run the same iteration: same
     status and number of iterations, bit-identical windows."""
     import torch
     inst = wl.config_parareal_trajectory(2001, nr=64, nt=256)
     nw, spw = 5, 20
     p = coarse.init_params(4, seed=3) if learned else None
-    kw = dict(windows=nw, steps_per_window=spw, kmax=3, tol=0.0, channels=4, kappa=1e-5, precision="fp32_storage",
+    kw = dict(windows=nw, steps_per_window=spw, kmax=3, tol=0.0, channels=4, kappa=1e-5, precision=precision,
               judge=False, fallback=False)
     U_py, hist = coarse.parareal(inst, p, **kw)
     U_c, res = coarse.parareal_native(inst, p, **kw)

@@ -244,6 +244,30 @@ def test_adaptive_dz_matches_oracle():
     assert werr(got, want) < 1e-10
 
 
+def test_adaptive_dz_fp32_cn64_tracks_fp64():
+    """FP32-CN64 with its own adaptive dz: the phase-rate rule sees the FP32 field, so its dz
+    sequence stays within the field error of the FP64 run's and the fields agree to the
+    FP32-CN64 accuracy."""
+    import torch
+    inst = wl.config_full(nr=48, nt=256)
+    a0 = wl.gaussian_field(inst) * math.sqrt(5e17 / inst["I0"])
+    kw = dict(adaptive=True, max_phase=0.05, dz_min=1e-6, dz_max=1e-2)
+    logs, fields = {}, {}
+    for prec in ("fp64", "fp32_cn64"):
+        plan = _plan(inst, prec, **kw)
+        log = torch.zeros(20, dtype=torch.float64, device=plan.device)
+        f = plan.pack(a0 if prec == "fp64" else a0.astype(np.complex64))
+        plan.propagate(f, 20, dz_log=log)
+        plan.sync()
+        logs[prec] = log.cpu().numpy()
+        fields[prec] = plan.unpack(f)[0].astype(np.complex128)
+    dzerr = float(np.max(np.abs(logs["fp32_cn64"] / logs["fp64"] - 1)))
+    e = werr(fields["fp32_cn64"], fields["fp64"])
+    say(f"  fp32-cn64 adaptive, 20 steps: dz {dzerr:.2e}, field {e:.2e}")
+    assert len(set(np.round(logs["fp64"], 12))) > 1
+    assert dzerr < 1e-5 and e < 20 * 1e-6
+
+
 def test_replay_dz_log_fp32():
     """FP32 run replaying the FP64 run's dz sequence lands on the FP64 trajectory."""
     import torch

@@ -182,7 +182,8 @@ fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, doub
 
 /* Launch configuration the plan chose: frequencies per workgroup and rows per thread of the
  * column solve (of the last nr bucket), elements per thread of the row kernel for the
- * largest nt (8; 16 at nt = 8192, and from nt = 2048 with FP64 arithmetic). */
+ * largest nt (8; 16 from nt = 4096, and from nt = 2048 with FP64 row arithmetic:
+ * FCN_FP64 and FCN_FP32_STORAGE). */
 fcn_status fcn_plan_tiles(fcn_plan_t plan, int32_t *col_tile, int32_t *col_rows, int32_t *row_elems);
 
 /* ------------------------------------------------------------------------------------

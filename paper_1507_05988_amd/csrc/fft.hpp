@@ -123,7 +123,8 @@ struct StockhamPass {
     static constexpr bool LAST = (NS * RADIX == NT);
 
     // v holds this pass's inputs: v[q*RADIX + r] = x[j + r*NT/RADIX], j = tr + q*T.
-    // tw: HALF = false: W_NT^k for k < NT; HALF = true: k < NT/2 (W^(k+NT/2) = -W^k).
+    // tw: HALF = false: W_NT^k for k < NT; HALF = true: k < NT/2 (W^(k+NT/2) = -W^k), an LDS
+    // copy with entry i at lpad(i).
     // PAIR: each twiddle is hi + lo (hi the table above, lo the same-size table after it),
     // so the transform's constants carry about twice the working precision.
     template <bool HALF, bool PAIR>
@@ -139,10 +140,13 @@ struct StockhamPass {
                     constexpr int TN = HALF ? NT / 2 : NT;  // entries of one table
                     const int ti = HALF ? (idx & (NT / 2 - 1)) : idx;
                     const bool neg = HALF && idx >= NT / 2;
-                    c2<R> w = tw[ti];
+                    // the LDS copy (HALF) is padded like the data rows: the twiddle indices of a
+                    // pass are multiples of NT/(NS*RADIX), which would put every lane of a
+                    // wavefront on the same bank
+                    c2<R> w = tw[HALF ? lpad(ti) : ti];
                     if (neg) w = mk<R>(-w.x, -w.y);
                     if constexpr (PAIR) {
-                        c2<R> wl = tw[TN + ti];
+                        c2<R> wl = tw[HALF ? lpad(TN + ti) : TN + ti];
                         if (neg) wl = mk<R>(-wl.x, -wl.y);
                         v[q * RADIX + r] = (DIR < 0) ? cmul_pair<R>(v[q * RADIX + r], w, wl)
                                                      : cmulc_pair<R>(v[q * RADIX + r], w, wl);
@@ -184,8 +188,9 @@ struct StockhamPass {
 };
 
 // Full transform, strided layout in and out.  DIR = -1 forward, +1 inverse (unscaled).
-// HALF: tw holds the first NT/2 table entries only.  PAIR: tw is followed by a table of the
-// same size holding the low parts of the twiddles.  Every thread of the workgroup must call
+// HALF: tw is an LDS copy of the first NT/2 table entries, entry i at lpad(i).  PAIR: tw is
+// followed by a table of the same size holding the low parts of the twiddles (with HALF:
+// low part of entry i at lpad(NT/2 + i)).  Every thread of the workgroup must call
 // it (it contains barriers).
 template <typename R, int NT, int E, int DIR, bool HALF = false, bool PAIR = false>
 __device__ __forceinline__ void row_fft(c2<R> (&v)[E], c2<R> *lds, int tr, const c2<R> *__restrict__ tw) {

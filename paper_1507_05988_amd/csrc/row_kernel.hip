@@ -365,8 +365,9 @@ struct RowCfg {
     // them into register spills)
     static constexpr bool PAIR = (FLAGS & RK_TW_PAIR) != 0;
     static constexpr int TWH = PAIR ? NT : NT / 2;
-    static constexpr bool TW_LDS = sizeof(c2<R>) == 8 && sizeof(c2<R>) * (size_t)(RPW * LROW + TWH) <= 150 * 1024;
-    static constexpr int TWN = TW_LDS ? TWH : 1;
+    static constexpr int TWP = TWH + TWH / 32;  // padded like the rows (lpad)
+    static constexpr bool TW_LDS = sizeof(c2<R>) == 8 && sizeof(c2<R>) * (size_t)(RPW * LROW + TWP) <= 150 * 1024;
+    static constexpr int TWN = TW_LDS ? TWP : 1;
     static_assert(!PAIR || sizeof(R) == 4, "twiddle pairs are for FP32 arithmetic");
 };
 
@@ -420,8 +421,8 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     const c2<R> *twp = tw;
     if constexpr (FFTS && Cfg::TW_LDS) {
         for (int i = tid; i < NT / 2; i += Cfg::THREADS) {
-            twl[i] = tw[i];
-            if constexpr (Cfg::PAIR) twl[NT / 2 + i] = tw[NT + i];  // low parts: table of NT after the NT highs
+            twl[lpad(i)] = tw[i];
+            if constexpr (Cfg::PAIR) twl[lpad(NT / 2 + i)] = tw[NT + i];  // low parts: table of NT after the NT highs
         }
         __syncthreads();
         twp = twl;

@@ -68,3 +68,28 @@ def test_oracle_matches_its_regression_values():
             assert math.isclose(cur[key], ref[key], rel_tol=1e-12, abs_tol=1e-300), (name, key)
         assert np.allclose(cur["fluence_first_8"], ref["fluence_first_8"], rtol=1e-12)
         assert np.allclose(cur["field_row0_first_4"], ref["field_row0_first_4"], rtol=1e-12, atol=0)
+
+
+def test_long_pulse_reference_is_current_and_consistent():
+    """tests/golden/long_pulse_reference.json (written by make_long_pulse_reference.py from the
+    oracle; the runs take up to 1.5 h, so they are not repeated here): written by the current
+    oracle source, checkpoints in order, z the sum of dz within [dz_min, dz_max], fluence and
+    samples of the stated sizes, energy non-increasing (absorption only removes energy)."""
+    import hashlib
+    g = _load("long_pulse_reference.json")
+    assert g["oracle_source_sha256"] == hashlib.sha256(oracle.source().encode()).hexdigest(), \
+        "the oracle's source changed: regenerate tests/golden/long_pulse_reference.json in a commit that names why"
+    cps = g["checkpoints"]
+    steps = [c["steps"] for c in cps]
+    assert steps == sorted(steps) and steps[0] == 100
+    inst = wl.config_long()
+    prev_e = math.inf
+    for c in cps:
+        n = c["steps"]
+        assert wl.LONG_DZ_MIN <= c["dz_min"] <= c["dz_last"] <= wl.LONG_DZ_MAX
+        assert n * c["dz_min"] * (1 - 1e-12) <= c["z"] <= n * wl.LONG_DZ_MAX * (1 + 1e-12)
+        assert len(c["fluence"]) == (inst["nr"] + c["fluence_stride"] - 1) // c["fluence_stride"]
+        assert len(c["field_samples"]) == 25
+        assert max(abs(complex(re, im)) for _, _, re, im in c["field_samples"]) <= c["abs_max"]
+        assert c["i_max"] >= c["i_axis"] > 0 and c["energy"] <= prev_e * (1 + 1e-12)
+        prev_e = c["energy"]

@@ -62,7 +62,7 @@ template <typename R, typename ST, int W, int L>
 __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     static_assert(L >= 4, "at least two interior rows per chunk");
     extern __shared__ unsigned char smem_raw[];
-    Eq<R> *red = reinterpret_cast<Eq<R> *>(smem_raw);  // [W][2S]
+    Eq<R> *red = reinterpret_cast<Eq<R> *>(smem_raw);  // [W][2S + 1]
 
     // Workgroups are dispatched round-robin over the 8 XCDs (b -> XCD b mod 8).  Give each
     // XCD a contiguous range of column tiles so tiles sharing 128-byte lines (W*sizeof < 128)
@@ -79,7 +79,9 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const int S = blockDim.x / W;
     const int nred = 2 * S;
     const int p = it.p0 + pl;
-    Eq<R> *myred = red + pl * nred;
+    // one spare entry per column: a stride of 2S entries would put the W columns of a
+    // wavefront on the same LDS banks (2S * sizeof(Eq) is a multiple of 256 bytes)
+    Eq<R> *myred = red + pl * (nred + 1);
 
     int64_t n = 0;
     double dz;
@@ -257,7 +259,7 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
     const int S = (nr + L - 1) / L;
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
-    const size_t shm = sizeof(Eq<R>) * (size_t)W * 2 * S;
+    const size_t shm = sizeof(Eq<R>) * (size_t)W * (2 * S + 1);
     hipExtLaunchKernelGGL((col_kernel<R, ST, W, L>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1, 0, a);
     return hipGetLastError();
 }

@@ -96,6 +96,24 @@ def timed_steps(plan, field, init, steps, torch):
     return total
 
 
+def copy_bandwidth(torch):
+    """Practical HBM bandwidth of the box: a 1 GiB device-to-device copy (read + write bytes),
+    best of 10, timed with events -- the attainable ceiling beside the 8 TB/s vendor peak."""
+    src = torch.ones(2 ** 27, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    nbytes = 2 * src.numel() * src.element_size()
+    del src, dst
+    return round(nbytes / best / 1e9, 1)
+
+
 def cpu_baseline(inst, a0, seconds: float):
     """The FP64 oracle on the host cores over a bounded sample of the same workload."""
     import oracle
@@ -527,6 +545,7 @@ def main():
                    "terms": "diffraction+GVD+Kerr(n2,n4)+plasma+MPA(K=8)+collisions"},
         "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1),
         "roofline": roofline,
+        "hbm_copy_gbs": copy_bandwidth(torch),
         "column_tiles": {k: {"col_tile": t["col_tile"], "col_rows": t["col_rows"],
                              "col_us": {kk: round(v * 1e3, 2) for kk, v in t["table"].items()}} for k, t in tiles.items()},
     }

@@ -127,9 +127,28 @@ def cpu_baseline(inst, a0, seconds: float):
     t0 = time.perf_counter()
     oracle.propagate(inst, a, n, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": pts * n / dt, "unit": "grid-pt z-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} FP64 oracle steps of the {inst['nr']}x{inst['nt']} full-model pulse "
-                      f"(after 1 warm step), {dt:.1f} s"}
+    out = {"value": pts * n / dt, "unit": "grid-pt z-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} FP64 oracle steps of the {inst['nr']}x{inst['nt']} full-model pulse "
+                     f"(after 1 warm step), {dt:.1f} s"}
+    # the same oracle on one thread (a few steps), and on the grid of the paper's timing
+    # example (Nr = 2112, Nt = 2048, Sec. 5.1 Table 2) on one thread and on all threads
+    from paper_1507_05988_amd import workloads as wl
+
+    n1 = max(1, int(min(seconds / 4, 5.0) / max(t1 * threads, 1e-6)))
+    t0 = time.perf_counter()
+    oracle.propagate(inst, a, n1, threads=1)
+    d1 = time.perf_counter() - t0
+    out["one_thread"] = {"value": pts * n1 / d1, "steps": n1, "seconds": round(d1, 2)}
+    pg = wl.config_paper_timing()
+    ag = wl.gaussian_field(pg)
+    rec = {"grid": f"{pg['nr']}x{pg['nt']}"}
+    for label, th, steps in (("all_threads", threads, 5), ("one_thread", 1, 1)):
+        t0 = time.perf_counter()
+        oracle.propagate(pg, ag, steps, threads=th)
+        d = time.perf_counter() - t0
+        rec[label] = {"threads": th, "seconds_per_step": round(d / steps, 3)}
+    out["paper_timing_grid"] = rec
+    return out
 
 
 def batched_sweep_measurement(torch):

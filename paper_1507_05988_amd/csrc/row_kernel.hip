@@ -128,6 +128,27 @@ __device__ __forceinline__ double seg_xor(double v, int d) {
     return __shfl_xor(v, d, W);
 }
 
+// Data-parallel-primitive (DPP) move of a double across the lanes of a wavefront: CTRL is a
+// GFX9 DPP control (row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143,
+// wave_shr:1 = 0x138); lanes without a source, or outside ROW_MASK, get `old`.  A register
+// move between lanes, where a shuffle is a round trip through the LDS crossbar.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double old, double v) {
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// One step of the inclusive scan: compose the map received from an earlier lane (pa, pb)
+// before this lane's (a, b) when `take`.
+__device__ __forceinline__ void scan_take(double &a, double &b, double pa, double pb, bool take) {
+    if (take) {
+        b = a * pb + b;
+        a = a * pa;
+    }
+}
+
 // Workgroup-shared scratch of the row kernel beyond the row buffers.
 struct RowScratch {
     double scan_a[16], scan_b[16];  // per-wave inclusive composition (cross-wave scan)
@@ -142,13 +163,21 @@ __device__ __forceinline__ double row_exclusive_scan(double a, double b, int tr,
     constexpr int W = T < 64 ? T : 64;
     const int lane = tr & (W - 1);
     // inclusive within the segment
+    if constexpr (W == 64) {
+        // whole wavefronts: shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the last
+        // lane of row 0 (2) into row 1 (3), then lane 31 into rows 2 and 3
+        scan_take(a, b, dpp_move<0x111>(1.0, a), dpp_move<0x111>(0.0, b), (lane & 15) >= 1);
+        scan_take(a, b, dpp_move<0x112>(1.0, a), dpp_move<0x112>(0.0, b), (lane & 15) >= 2);
+        scan_take(a, b, dpp_move<0x114>(1.0, a), dpp_move<0x114>(0.0, b), (lane & 15) >= 4);
+        scan_take(a, b, dpp_move<0x118>(1.0, a), dpp_move<0x118>(0.0, b), (lane & 15) >= 8);
+        scan_take(a, b, dpp_move<0x142, 0xa>(1.0, a), dpp_move<0x142, 0xa>(0.0, b), (lane & 16) != 0);
+        scan_take(a, b, dpp_move<0x143, 0xc>(1.0, a), dpp_move<0x143, 0xc>(0.0, b), lane >= 32);
+    } else {
 #pragma unroll
-    for (int d = 1; d < W; d <<= 1) {
-        const double pa = seg_up<W>(a, d);
-        const double pb = seg_up<W>(b, d);
-        if (lane >= d) {
-            b = a * pb + b;
-            a = a * pa;
+        for (int d = 1; d < W; d <<= 1) {
+            const double pa = seg_up<W>(a, d);
+            const double pb = seg_up<W>(b, d);
+            scan_take(a, b, pa, pb, lane >= d);
         }
     }
     double pre_a = 1.0, pre_b = 0.0;  // composition of the earlier waves of this row
@@ -168,27 +197,64 @@ __device__ __forceinline__ double row_exclusive_scan(double a, double b, int tr,
         b = a * pre_b + b;
         a = a * pre_a;
     }
-    // exclusive: inclusive of the previous thread
-    double eb = seg_up<W>(b, 1);
-    if (lane == 0) eb = pre_b;  // first lane of a wave: prefix of earlier waves (0 for tr = 0)
-    return eb;
+    // exclusive: inclusive of the previous thread; the first lane of a wave takes the prefix
+    // of the earlier waves (0 for tr = 0)
+    if constexpr (W == 64) {
+        return dpp_move<0x138>(pre_b, b);
+    } else {
+        double eb = seg_up<W>(b, 1);
+        if (lane == 0) eb = pre_b;
+        return eb;
+    }
 }
 
 // Sum / max reductions over the T threads of a row; result valid in every thread.
 template <int T>
 __device__ __forceinline__ DiagAcc row_reduce(DiagAcc v, int tr, RowScratch &sh) {
     constexpr int W = T < 64 ? T : 64;
+    if constexpr (W == 64) {
+        // whole wavefronts: the same DPP pattern as the scan accumulates the wavefront's
+        // total in lane 63
+        const int lane = tr & 63;
+        auto take = [&](DiagAcc o, bool t) {
+            if (t) {
+                v.sum += o.sum;
+                v.imax = fmax(v.imax, o.imax);
+                v.rmax = fmax(v.rmax, o.rmax);
+                v.phimax = fmax(v.phimax, o.phimax);
+            }
+        };
+#define FCN_DIAG_MOVE(CTRL, RM) \
+    DiagAcc{dpp_move<CTRL, RM>(0.0, v.sum), dpp_move<CTRL, RM>(0.0, v.imax), dpp_move<CTRL, RM>(0.0, v.rmax), \
+            dpp_move<CTRL, RM>(0.0, v.phimax)}
+        take(FCN_DIAG_MOVE(0x111, 0xf), (lane & 15) >= 1);
+        take(FCN_DIAG_MOVE(0x112, 0xf), (lane & 15) >= 2);
+        take(FCN_DIAG_MOVE(0x114, 0xf), (lane & 15) >= 4);
+        take(FCN_DIAG_MOVE(0x118, 0xf), (lane & 15) >= 8);
+        take(FCN_DIAG_MOVE(0x142, 0xa), (lane & 16) != 0);
+        take(FCN_DIAG_MOVE(0x143, 0xc), lane >= 32);
+#undef FCN_DIAG_MOVE
+        if constexpr (T == 64) {  // one wavefront per row: every lane takes lane 63's total
+            auto bcast = [](double x) {
+                const long long b = __double_as_longlong(x);
+                const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+                return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+            };
+            v = DiagAcc{bcast(v.sum), bcast(v.imax), bcast(v.rmax), bcast(v.phimax)};
+        }
+    } else {
 #pragma unroll
-    for (int d = W / 2; d >= 1; d >>= 1) {
-        v.sum += seg_xor<W>(v.sum, d);
-        v.imax = fmax(v.imax, seg_xor<W>(v.imax, d));
-        v.rmax = fmax(v.rmax, seg_xor<W>(v.rmax, d));
-        v.phimax = fmax(v.phimax, seg_xor<W>(v.phimax, d));
+        for (int d = W / 2; d >= 1; d >>= 1) {
+            v.sum += seg_xor<W>(v.sum, d);
+            v.imax = fmax(v.imax, seg_xor<W>(v.imax, d));
+            v.rmax = fmax(v.rmax, seg_xor<W>(v.rmax, d));
+            v.phimax = fmax(v.phimax, seg_xor<W>(v.phimax, d));
+        }
     }
     if constexpr (T > 64) {
         const int wave = threadIdx.x >> 6;
         const int first_wave = wave - (tr >> 6);
-        if ((tr & 63) == 0) {
+        if ((tr & 63) == 63) {  // the lane holding the wavefront's total
             sh.diag[wave][0] = v.sum;
             sh.diag[wave][1] = v.imax;
             sh.diag[wave][2] = v.rmax;

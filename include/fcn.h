@@ -272,7 +272,8 @@ fcn_status fcn_parareal_update(const void *g_new, const void *f_old, const void 
  * and a `fine_serial` plan (one instance, dz of the fine steps), U is replaced by the serial
  * fine solution.
  * Plans: `fine` holds `windows` instances of the pulse back to back; `coarse` and
- * `fine_serial` one; all FP32 or FP32 storage (complex64 fields), bound to one stream, as is
+ * `fine_serial` one; all in an FP32-field mode (FCN_FP32, FCN_FP32_STORAGE or FCN_FP32_CN64:
+ * complex64 fields), bound to one stream, as is
  * the network (bound for at least one nr x nt window).  u_dev: [windows + 1][nr][nt]
  * complex64, U_0 in, U_1..U_windows out.  workspace: fcn_parareal_workspace_size bytes,
  * 256-byte aligned, caller-owned.  Synchronous: returns when the result is final.

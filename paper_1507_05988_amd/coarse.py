@@ -279,7 +279,7 @@ def parareal(inst: dict, net_params=None, windows=wl.PARAREAL_WINDOWS, steps_per
     history[k] = dict(iter, change, error (vs `reference[j]` for U[j+1] if given), seconds);
     iteration 0 is the coarse sweep alone.  The last record carries `status`: "converged",
     "diverging", "nonfinite" (a NaN or Inf change; the iterate is discarded), "kmax" or
-    "fallback".  `precision` ("fp32" or "fp32_storage") is that of the
+    "fallback".  `precision` ("fp32", "fp32_storage" or "fp32_cn64") is that of the
     fine and classical coarse FCN steps; fields are complex64 either way."""
     import torch
 

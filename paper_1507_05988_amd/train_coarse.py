@@ -91,7 +91,7 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=len(HELD_OUT), help="held-out trajectories to evaluate")
     ap.add_argument("--out", default=None)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp32_storage", choices=["fp32", "fp32_storage"],
+    ap.add_argument("--precision", default="fp32_storage", choices=["fp32", "fp32_storage", "fp32_cn64"],
                     help="precision of the FCN steps that generate the targets")
     args = ap.parse_args(argv)
 

@@ -29,6 +29,12 @@ MUTANTS = [
      "if (orc_nl_half(pp, field, dz, nthreads)) return 1;"),
     ("energy_axis_weight", "double e = 0.125 * rowsum[0];", "double e = 0.25 * rowsum[0];"),
     ("adaptive_lag", "double phi_lag = (n == 0) ? diag[4] : phi_prev;", "double phi_lag = diag[4];"),
+    ("coll_sign", "nhat += -(pp->sigma_c / 2.0) * rho;", "nhat += (pp->sigma_c / 2.0) * rho;"),
+    ("coll_half_dropped", "nhat += -(pp->sigma_c / 2.0) * rho;", "nhat += -pp->sigma_c * rho;"),
+    ("kerr_n6_dropped", "pp->n6 * pow(inten, 3.0)", "0.0 * pow(inten, 3.0)"),
+    ("kerr_n8_dropped", "pp->n8 * pow(inten, 4.0)", "0.0 * pow(inten, 4.0)"),
+    ("kerr_n6_power", "pp->n6 * pow(inten, 3.0)", "pp->n6 * pow(inten, 2.0)"),
+    ("mpa_half_dropped", "nhat += -(dv->betaK / 2.0) * pow(", "nhat += -(dv->betaK) * pow("),
 ]
 
 
@@ -57,7 +63,10 @@ def test_pins_catch_planted_mistake(tmp_path, name, orig, bad):
     with oracle.use_library(path):
         for tname, fn, kw in _pin_tests():
             try:
-                fn(oracle, **kw)
+                if "orc" in inspect.signature(fn).parameters:
+                    fn(orc=oracle, **kw)
+                else:
+                    fn(**kw)
             except Exception:  # an assertion, or a non-finite result that numpy trips on
                 caught.append(tname)
                 break

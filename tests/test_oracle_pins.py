@@ -403,3 +403,151 @@ def test_energy_diagnostic_is_the_conserved_norm(orc):
     e1 = orc.diagnostics(inst, b)["energy"]
     assert abs(e1 / e0 - 1) < 1e-13
     assert np.max(np.abs(b - a)) > 0.01 * np.max(np.abs(a))
+
+
+# ------------------------------------- collisional absorption and higher-order Kerr terms
+
+def _rk4_density(inst, x, nt):
+    """Density of the RK4 integration at constant intensity, from the mathematics alone: for a
+    constant rate g the classical RK4 step multiplies (rho_at - rho) by the degree-4 Taylor
+    polynomial of e^{-x}, x = g dtau, so rho_p = rho_at (1 - r4(x)^p) from rho_0 = 0."""
+    r4 = 1 - x + x ** 2 / 2 - x ** 3 / 6 + x ** 4 / 24
+    return inst["rho_at"] * (1 - r4 ** np.arange(nt))
+
+
+def _intensity_for(inst, x, nt):
+    dtau = (inst["t_max"] - inst["t_min"]) / nt
+    return (x / (inst["sigma_K"] * dtau)) ** (1.0 / inst["K"])
+
+
+@pytest.mark.parametrize("terms", [COLL, COLL | MPA])
+def test_collisional_absorption_plane_wave(orc, terms):
+    """Reading of the collisional term (not in the paper): N gains -(sigma_c/2) rho, so one
+    nonlinear sub-step of length h on a plane wave scales the intensity by
+    exp(-h (sigma_c rho_p + beta_K I^(K-1))) (Eq. nonlinearpart with the MPA term, Eq.
+    ionization for rho) and leaves the phase alone.  rho_p comes from the closed form of the
+    RK4 recurrence at constant intensity, not from the oracle's density routine."""
+    nt = 64
+    inst = wl.config_full(nr=4, nt=nt)
+    x = 0.1
+    I = _intensity_for(inst, x, nt)
+    phase0 = np.exp(0.3j)
+    a = np.full((4, nt), math.sqrt(I) * phase0, dtype=complex)
+    a[-1] = 0
+    h = 0.02
+    out = orc.nl_half(inst, a, h, terms=terms)
+    rho = _rk4_density(inst, x, nt)
+    hbar, c = 1.054571817e-34, 299792458.0
+    w0 = 2 * math.pi * c / inst["lambda0"]
+    beta = inst["K"] * hbar * w0 * inst["sigma_K"] * inst["rho_at"]
+    loss = inst["sigma_c"] * rho + (beta * I ** (inst["K"] - 1) if terms & MPA else 0.0)
+    want = I * np.exp(-h * loss)
+    got = np.abs(out[0]) ** 2
+    assert np.max(np.abs(got / want - 1)) < 1e-13
+    assert np.max(np.abs(np.angle(out[:-1] / phase0))) < 1e-14
+    # the term is resolved: the intensity falls by several percent along the row
+    assert want[-1] < 0.8 * I and rho[-1] > 0.99 * inst["rho_at"]
+
+
+def test_energy_bookkeeping_after_a_half_step(orc):
+    """After one nonlinear sub-step of length h the energy is
+    2 pi dr^2 dtau sum_m w_m sum_p |A_mp|^2 exp(2 h Re N_mp): the Kerr and plasma terms of N
+    (Eq. nonlinearpart) only turn the phase, the absorption terms (MPA, collisions) set the
+    modulus.  Re N = -(beta_K/2) I^(K-1) - (sigma_c/2) rho with rho from the oracle's density
+    routine (pinned above by its closed forms)."""
+    inst = wl.config_full(nr=24, nt=128)
+    a = wl.gaussian_field(inst) * math.sqrt(1.5e18 / inst["I0"])
+    rng = np.random.default_rng(21)
+    a *= np.exp(2j * np.pi * rng.random(a.shape))
+    h = 2.5e-3
+    out = orc.nl_half(inst, a, h)
+    hbar, c = 1.054571817e-34, 299792458.0
+    w0 = 2 * math.pi * c / inst["lambda0"]
+    beta = inst["K"] * hbar * w0 * inst["sigma_K"] * inst["rho_at"]
+    inten = np.abs(a) ** 2
+    rho = np.stack([orc.rho_row(inst, row) for row in inten])
+    re_n = -beta / 2 * inten ** (inst["K"] - 1) - inst["sigma_c"] / 2 * rho
+    dr = inst["r_max"] / (inst["nr"] - 1)
+    dtau = (inst["t_max"] - inst["t_min"]) / inst["nt"]
+    w = np.arange(inst["nr"], dtype=float)
+    w[0] = 0.125
+    want = 2 * math.pi * dr ** 2 * dtau * np.sum(w[:, None] * inten * np.exp(2 * h * re_n))
+    got = orc.diagnostics(inst, out)["energy"]
+    assert abs(got / want - 1) < 1e-13
+    e0 = orc.diagnostics(inst, a)["energy"]
+    assert got < (1 - 1e-4) * e0  # absorption is resolved
+
+
+def test_kerr_plane_wave_phase_all_orders(orc):
+    """The Kerr sum runs to j = 4 (Eq. nlse): a plane wave with diffraction and GVD off keeps
+    its modulus and turns by k0 (n2 I + n4 I^2 + n6 I^3 + n8 I^4) z / n0.  The coefficients are
+    synthetic, of alternating sign, sized so every order turns the phase by more than 1e-6 rad."""
+    inst = _inst(nr=8, nt=16, n2=3.2e-23, n4=-3.6e-42, terms=KERR)
+    inst.update(n6=4e-60, n8=-2e-77)
+    I0 = 5e16
+    a = np.full((8, 16), math.sqrt(I0), dtype=complex)
+    a[-1] = 0
+    z = 0.1
+    out = orc.propagate(inst, a, 10, dz=z / 10)
+    k0 = 2 * math.pi / inst["lambda0"]
+    orders = [inst[k] * I0 ** j for j, k in ((1, "n2"), (2, "n4"), (3, "n6"), (4, "n8"))]
+    phase = k0 * sum(orders) * z
+    want = math.sqrt(I0) * np.exp(1j * phase)
+    assert np.max(np.abs(out[:-1] - want)) <= 1e-13 * math.sqrt(I0)
+    assert min(abs(k0 * o * z) for o in orders) > 1e-6
+
+
+def test_collisional_cross_section_is_the_drude_value():
+    """Reading of the collisional term: sigma_c = k0 w0 tau_c / (n0 rho_c (1 + w0^2 tau_c^2)) with
+    tau_c = 350 fs at 800 nm (a literature collision time; the paper has no collisional term).
+    The stored input coefficient is re-derived here from CODATA constants."""
+    c, me, qe, eps0 = 299792458.0, 9.1093837015e-31, 1.602176634e-19, 8.8541878128e-12
+    lam, n0, tau_c = 800e-9, 1.0, 350e-15
+    k0 = 2 * math.pi * n0 / lam
+    w0 = 2 * math.pi * c / lam
+    rho_c = eps0 * me * w0 ** 2 / qe ** 2
+    sigma = k0 * w0 * tau_c / (n0 * rho_c * (1 + (w0 * tau_c) ** 2))
+    assert abs(sigma / wl.SIGMA_C_800NM - 1) < 1e-12
+    assert abs(rho_c / 1.742e27 - 1) < 1e-3  # the critical density quoted for 800 nm
+
+
+# ---------------------------------- stability limit of the paper's density integration
+
+def test_rk4_density_step_stability_limit(orc):
+    """The explicit RK4 step of Eq. ionization at constant rate multiplies (rho_at - rho) by
+    r4(x), x = sigma_K I^K dtau; |r4| <= 1 only for x <= 2.785.  Beyond it the density runs
+    away from rho_at geometrically: a property of the method at this dtau, not of any kernel."""
+    nt = 64
+    inst = wl.config_full(nr=4, nt=nt)
+    xs = np.linspace(2.70, 2.80, 11)
+    r4 = 1 - xs + xs ** 2 / 2 - xs ** 3 / 6 + xs ** 4 / 24
+    limit = xs[np.argmax(r4 > 1)]
+    assert 2.78 <= limit <= 2.79
+    for x, stable in ((2.7, True), (3.0, False)):
+        rho = orc.rho_row(inst, np.full(nt, _intensity_for(inst, x, nt)))
+        assert np.allclose(rho, _rk4_density(inst, x, nt), rtol=1e-12, atol=1e-12 * inst["rho_at"])
+        inside = np.all((rho >= -1e-6 * inst["rho_at"]) & (rho <= 1.0001 * inst["rho_at"]))
+        assert inside == stable
+
+
+def test_full_model_grid_density_instability_in_the_oracle(orc):
+    """On the full-model time grid (Nt = 2048 over [-400, 400) fs, dtau = 0.39 fs) the stability
+    limit x = 2.785 is reached at I = 1.99e18 W/m^2.  A row whose peak exceeds it (a 30 fs spike
+    of 2.1e18 W/m^2, the kind of refocusing spike the full-model pulse reaches after its
+    collapse) drives the oracle's own density far outside [0, rho_at] and its field to
+    overflow within one nonlinear half step, while a 1.9e18 W/m^2 spike stays bounded."""
+    inst = wl.config_full(nr=4, nt=2048)
+    dtau = (inst["t_max"] - inst["t_min"]) / 2048
+    i_lim = (2.785 / (inst["sigma_K"] * dtau)) ** (1 / inst["K"])
+    assert abs(i_lim / 1.99e18 - 1) < 0.01
+    t = inst["t_min"] + np.arange(2048) * dtau
+    for ipk, stable in ((1.9e18, True), (2.1e18, False)):
+        inten = ipk * np.exp(-2 * (t / 30e-15) ** 2)
+        rho = orc.rho_row(inst, inten)
+        a = np.zeros((4, 2048), dtype=complex)
+        a[0] = a[1] = np.sqrt(inten)
+        with np.errstate(all="ignore"):
+            out = orc.nl_half(inst, a, inst["dz"] / 2)
+            bounded = bool(np.all(np.isfinite(rho)) and rho.min() >= 0 and rho.max() <= inst["rho_at"])
+        assert bounded == stable
+        assert bool(np.all(np.isfinite(out))) == stable

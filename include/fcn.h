@@ -23,7 +23,8 @@
  *    fcn_plan_destroy.
  *  - Asynchrony: compute entry points enqueue work on the bound stream and return at once.
  *    Argument errors are reported synchronously by the return code; numerical failure
- *    (a non-finite intensity seen on the device) is reported by fcn_sync.
+ *    (a non-finite intensity, or a density step outside its stability region, seen on the
+ *    device) is reported by fcn_sync.
  *  - A plan is not thread-safe.  fcn_last_error(plan) gives a text for the last failure.
  */
 #ifndef FCN_H
@@ -45,7 +46,11 @@ typedef enum {
     FCN_E_HIP = 3,         /* a HIP runtime call failed */
     FCN_E_NONFINITE = 4,   /* the device saw a non-finite intensity */
     FCN_E_STATE = 5,       /* call order violated (e.g. step before bind) */
-    FCN_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+    FCN_E_UNSUPPORTED = 6, /* valid request this build does not implement */
+    FCN_E_UNSTABLE = 7     /* an RK4 step of the density (Eq. ionization) left its stability
+                              region: sigma_K I^K dtau beyond about 2.785 somewhere on the grid,
+                              so the density runs out of [0, rho_at]; a property of the method at
+                              that time step, reported by fcn_sync */
 } fcn_status;
 
 /* Term switches of the operators (Eqs. linearpart and nonlinearpart). */
@@ -87,8 +92,10 @@ typedef struct {
 } fcn_instance;
 
 typedef struct {
-    int32_t precision;       /* FCN_FP64; FCN_FP32 (field, FFT, CN and exponentials in FP32;
-                                density scan, operator exponents and diagnostics in FP64); or
+    int32_t precision;       /* FCN_FP64; FCN_FP32 (field, FFTs, CN solve and nonlinear step
+                                in FP32, the step on the scaled intensity I/I_ref; density scan
+                                and diagnostics in FP64, and h N formed in FP64 when a density
+                                term is on); or
                                 FCN_FP32_STORAGE (FP32 field, FP64 arithmetic);
                                 FCN_FP32_CN64 (FP32 field and row pass with twiddle pairs,
                                 FP64 column solve) */
@@ -96,7 +103,9 @@ typedef struct {
                                 dz_max) with Phi the peak nonlinear phase rate of A^{n-1} */
     double max_phase;        /* [rad] per step, adaptive mode */
     double dz_min, dz_max;   /* [m], adaptive mode */
-    int32_t use_graph;       /* 1: replay the step body as a captured HIP graph */
+    int32_t use_graph;       /* 1: replay the step body as a captured HIP graph (needs a non-NULL
+                                stream; fcn_step, and fcn_propagate without diagnostics records
+                                or dz log: those calls run eagerly) */
     int32_t col_tile;        /* 0: auto; else frequencies per column workgroup (1, 2, 4, 8, 16 or 32) */
     int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (8 or 16) */
     int32_t reserved;        /* must be 0 */
@@ -162,8 +171,9 @@ fcn_status fcn_diagnostics(fcn_plan_t plan, const void *field_dev, double *diag_
 enum { FCN_STAGE_FFT = 0, FCN_STAGE_IFFT = 1, FCN_STAGE_CN = 2, FCN_STAGE_NL = 3 };
 fcn_status fcn_stage(fcn_plan_t plan, int32_t stage, void *field_dev, double length);
 
-/* Waits for the bound stream; returns FCN_E_NONFINITE if the device flagged a non-finite
- * intensity since bind (the flag is then cleared). */
+/* Waits for the bound stream; returns FCN_E_UNSTABLE if an RK4 density step left its
+ * stability region since the last report, else FCN_E_NONFINITE if the device flagged a
+ * non-finite intensity (both flags are then cleared). */
 fcn_status fcn_sync(fcn_plan_t plan);
 
 /* Text of the last error on this plan (valid until the next call on it); "" if none. */

@@ -52,7 +52,7 @@ struct DevState {
     int64_t cnt_col;        // step index read by the column kernels
     int64_t cnt_row;        // step index read by the row kernels
     int32_t nonfinite;      // set to 1 when a non-finite intensity is seen
-    int32_t pad;
+    int32_t unstable;       // set to 1 when an RK4 density step leaves [0, 1] (see the row kernel)
     double z_pad[5];
 };
 

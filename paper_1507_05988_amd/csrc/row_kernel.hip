@@ -17,10 +17,12 @@
 // linear equation is the affine map rho -> (1 - S_p) rho + S_p rho_at with S_p written out
 // below, so the density along the row is an exclusive scan of affine maps: each thread
 // composes the maps of its E contiguous points, the workgroup scans the compositions in
-// FP64 with wavefront shuffles, then each thread replays its points.  The update is
-// A <- A exp(h Re N) (cos(h Im N) + i sin(h Im N)) with N of Eq. nonlinearpart.
-// Intensity, density, N and the diagnostics are FP64 in both precisions; the FP32 path
-// rounds h Re N and h Im N to FP32 before expf/sincosf.
+// FP64 (DPP lane moves inside a wavefront, LDS across wavefronts), then each thread replays
+// its points.  The update is A <- A exp(h Re N) (cos(h Im N) + i sin(h Im N)) with N of
+// Eq. nonlinearpart.  FP64 kernels compute everything in FP64.  FP32 kernels compute the
+// intensity, the Kerr rate, the multiphoton term and the RK4 factors in FP32 on the scaled
+// intensity u = I / I_ref (NlPoint<float>), compose, scan and replay the density in FP64,
+// form h N in FP64 when a density term is on, and accumulate the diagnostics in FP64.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
@@ -157,9 +159,11 @@ struct RowScratch {
 
 // Exclusive scan over the T threads of a row of the affine maps (a, b): x -> a x + b,
 // earlier threads applied first.  Returns b of the exclusive prefix (the density at the
-// thread's first point, the row starting from rho = 0).  All threads must call it.
+// thread's first point, the row starting from rho = 0); `incl` receives b of the inclusive
+// prefix, which is bit for bit the value the next thread receives as its exclusive prefix.
+// All threads must call it.
 template <int T>
-__device__ __forceinline__ double row_exclusive_scan(double a, double b, int tr, RowScratch &sh) {
+__device__ __forceinline__ double row_exclusive_scan(double a, double b, int tr, RowScratch &sh, double &incl) {
     constexpr int W = T < 64 ? T : 64;
     const int lane = tr & (W - 1);
     // inclusive within the segment
@@ -197,6 +201,7 @@ __device__ __forceinline__ double row_exclusive_scan(double a, double b, int tr,
         b = a * pre_b + b;
         a = a * pre_a;
     }
+    incl = b;
     // exclusive: inclusive of the previous thread; the first lane of a wave takes the prefix
     // of the earlier waves (0 for tr = 0)
     if constexpr (W == 64) {
@@ -337,14 +342,17 @@ struct NlPoint<float> {
 //  scan = true: c[] holds the contiguous points tr*E + k of the row and nx the point after
 //    the chunk (pre-update; for the last thread any value, it only feeds the unused last
 //    interval).  The density follows from the RK4 affine maps scanned over the row.  With
-//    upd_next, nx is also advanced with the density reached at the end of the chunk, so the
-//    next sub-step has its neighbour intensity without another LDS exchange.
+//    upd_next, nx is also advanced, with the density its own thread uses, so the next
+//    sub-step has its neighbour intensity without another LDS exchange.
 //  scan = false (no density term in the workgroup): pointwise, any layout, nx unused.
+// The exact density step has S = 1 - exp(-int g dt) in [0, 1); an RK4 factor S outside [0, 1]
+// (a non-negative rate with sigma_K I^K dtau beyond the method's stability limit, 2.785 at
+// constant rate) sets *unstable: the density then leaves [0, rho_at] and runs away.
 // Must be called by every thread of the workgroup (the scan holds barriers when T > 64).
 template <typename R, int T, int E>
 __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevInst &in, R h, bool apply,
                                             bool diag, bool scan, bool upd_next, DiagAcc &acc, int tr,
-                                            RowScratch &sh) {
+                                            RowScratch &sh, int32_t *unstable) {
     using S_t = decltype(NlPoint<R>{}.dt_g(in));
     const bool k1 = in.need_ik1 != 0.0;
     NlPoint<R> pt[E];
@@ -361,6 +369,7 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevI
         S_t S[E];
         double ca = 1.0, cb = 0.0;
         S_t a0 = pt[0].dt_g(in);
+        bool bad = false;
 #pragma unroll
         for (int k = 0; k < E; k++) {
             const NlPoint<R> &p1 = (k + 1 < E) ? pt[k + 1] : pn;
@@ -374,19 +383,21 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevI
             const S_t u4 = one - ah * u3;
             const S_t sv = (a0 + S_t(2) * ah * u2 + S_t(2) * ah * u3 + a1 * u4) * S_t(1.0 / 6.0);
             S[k] = need_rho ? sv : S_t(0);
+            // the row's last interval (last thread, last point) wraps to t_min and is never used
+            if (!(S[k] >= S_t(0) && S[k] <= S_t(1)) && (k + 1 < E || tr + 1 < T)) bad = true;
             const double sd = (double)S[k];
             cb = (1.0 - sd) * cb + sd * ra;  // compose after the chunk's earlier steps
             ca = (1.0 - sd) * ca;
             a0 = a1;
         }
-        double r = row_exclusive_scan<T>(ca, cb, tr, sh);
+        if (bad) atomicOr(unstable, 1);
+        double r = row_exclusive_scan<T>(ca, cb, tr, sh, rho_end);
 #pragma unroll
         for (int k = 0; k < E; k++) {
             rho[k] = r;
             const double sd = (double)S[k];
             r = (1.0 - sd) * r + sd * ra;
         }
-        rho_end = r;
     } else {
 #pragma unroll
         for (int k = 0; k < E; k++) rho[k] = 0.0;
@@ -408,6 +419,9 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevI
                 c[k] = pt[k].apply(c[k], in, h, rho[k]);
         }
     }
+    // the neighbour's first point with the density its own thread uses (the scan's prefix, not
+    // this thread's replayed value, which may differ in the last bit): a fused pass then
+    // advances every point exactly as two separate passes would
     if (apply && scan && upd_next) nx = pn.apply(nx, in, h, rho_end);
 }
 
@@ -519,8 +533,10 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 #pragma unroll
             for (int k = 0; k < E; k++) c[k] = row_lds[lpad(tr * E + k)];
             c2<R> nx = row_lds[lpad(tr < T - 1 ? tr * E + E : 0)];
-            if constexpr (DO_A) nl_sub_step<R, T, E>(c, nx, in, ha, true, false, true, true, acc, tr, sh);
-            if constexpr (DO_B || DO_D) nl_sub_step<R, T, E>(c, nx, in, hb, DO_B, DO_D, true, false, acc, tr, sh);
+            int32_t *unst = &a.state->unstable;
+            if constexpr (DO_A) nl_sub_step<R, T, E>(c, nx, in, ha, true, false, true, true, acc, tr, sh, unst);
+            if constexpr (DO_B || DO_D)
+                nl_sub_step<R, T, E>(c, nx, in, hb, DO_B, DO_D, true, false, acc, tr, sh, unst);
             if constexpr ((FLAGS & RK_STORE) != 0) {
                 __syncthreads();
 #pragma unroll
@@ -531,8 +547,10 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
             }
         } else {
             c2<R> unused = czero<R>();
-            if constexpr (DO_A) nl_sub_step<R, T, E>(v, unused, in, ha, true, false, false, false, acc, tr, sh);
-            if constexpr (DO_B || DO_D) nl_sub_step<R, T, E>(v, unused, in, hb, DO_B, DO_D, false, false, acc, tr, sh);
+            int32_t *unst = &a.state->unstable;
+            if constexpr (DO_A) nl_sub_step<R, T, E>(v, unused, in, ha, true, false, false, false, acc, tr, sh, unst);
+            if constexpr (DO_B || DO_D)
+                nl_sub_step<R, T, E>(v, unused, in, hb, DO_B, DO_D, false, false, acc, tr, sh, unst);
         }
         if constexpr (DO_D) {
             acc = row_reduce<T>(acc, tr, sh);
@@ -713,6 +731,7 @@ __global__ void init_state_kernel(DevState *state, unsigned long long *phi_slot,
         state->cnt_col = n0;
         state->cnt_row = n0;
         state->nonfinite = 0;
+        state->unstable = 0;
     }
     if (i < 2 * batch) {
         phi_slot[i] = 0ull;
@@ -729,7 +748,10 @@ hipError_t launch_init_state(DevState *state, unsigned long long *phi_slot, doub
     return hipGetLastError();
 }
 
-__global__ void clear_flag_kernel(DevState *state) { state->nonfinite = 0; }
+__global__ void clear_flag_kernel(DevState *state) {
+    state->nonfinite = 0;
+    state->unstable = 0;
+}
 
 hipError_t launch_clear_flag(DevState *state, hipStream_t s) {
     hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, state);

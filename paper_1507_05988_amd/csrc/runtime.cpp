@@ -543,7 +543,8 @@ fcn_status run_steps(fcn_plan_t p, void *field, int64_t nsteps, double *diag, in
         if (e != hipSuccess) return hip_fail(p, e, "finalize");
     }
     // graphs need a capturable (non-default) stream; they hold the field pointer
-    const bool graph_ok = p->opt.use_graph && !want_diag && p->stream != nullptr;
+    // and hold their kernels' arguments, so calls with a dz log (adaptive logging or replay) run eagerly
+    const bool graph_ok = p->opt.use_graph && !want_diag && p->stream != nullptr && dz_log == nullptr;
     if (graph_ok && p->graph_exec && p->graph_field != field) {
         hipGraphExecDestroy(p->graph_exec);
         p->graph_exec = nullptr;
@@ -760,12 +761,16 @@ fcn_status fcn_sync(fcn_plan_t p) {
     if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "hipStreamSynchronize");
-    int32_t flag = 0;
-    e = hipMemcpy(&flag, &p->d_state()->nonfinite, sizeof flag, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(p, e, "read flag");
-    if (flag) {
+    int32_t flags[2] = {0, 0};  // DevState::nonfinite, DevState::unstable (adjacent)
+    e = hipMemcpy(flags, &p->d_state()->nonfinite, sizeof flags, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(p, e, "read flags");
+    if (flags[0] || flags[1]) {
         e = launch_clear_flag(p->d_state(), p->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (flags[1])
+            return fail(p, FCN_E_UNSTABLE,
+                        "an RK4 density step left its stability region (sigma_K I^K dtau beyond about 2.785)%s",
+                        flags[0] ? "; the field then became non-finite" : "");
         return fail(p, FCN_E_NONFINITE, "non-finite intensity in the field");
     }
     return FCN_OK;

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcn.so")
 
-FCN_OK, FCN_E_ARG, FCN_E_SIZE, FCN_E_HIP, FCN_E_NONFINITE, FCN_E_STATE, FCN_E_UNSUPPORTED = range(7)
+FCN_OK, FCN_E_ARG, FCN_E_SIZE, FCN_E_HIP, FCN_E_NONFINITE, FCN_E_STATE, FCN_E_UNSUPPORTED, FCN_E_UNSTABLE = range(8)
 FCN_FP64, FCN_FP32, FCN_FP32_STORAGE, FCN_FP32_CN64 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FCN_FP64, "fp32": FCN_FP32, "fp32_storage": FCN_FP32_STORAGE, "fp32_cn64": FCN_FP32_CN64}
 STAGE_FFT, STAGE_IFFT, STAGE_CN, STAGE_NL = 0, 1, 2, 3

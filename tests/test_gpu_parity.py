@@ -343,20 +343,60 @@ def test_graph_replay_equals_eager():
         assert np.array_equal(eager.unpack(fe)[0].view(np.uint32), graph.unpack(fg)[0].view(np.uint32))
 
 
-def test_step_splitting_is_exact():
-    """step(n) then step(m) equals step(n+m) bitwise (state carried in the workspace)."""
-    inst = wl.config_full(nr=40, nt=256)
+def test_graph_plans_with_dz_log_match_eager():
+    """A graph-enabled plan given a dz log (adaptive logging, or replay) runs eagerly: fields and
+    logs equal the eager plan's bit for bit, every step's dz is logged, and replay follows the log."""
+    import torch
+    inst = wl.config_full(nr=48, nt=256)
     a0 = wl.gaussian_field(inst) * math.sqrt(5e17 / inst["I0"])
-    p = _plan(inst, "fp64")
+    kw = dict(adaptive=True, max_phase=0.05, dz_min=1e-6, dz_max=1e-2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        out = {}
+        for g in (False, True):
+            plan = _plan(inst, "fp64", use_graph=g, stream=stream, **kw)
+            log = torch.zeros(40, dtype=torch.float64, device=plan.device)
+            f = plan.pack(a0)
+            plan.propagate(f, 40, dz_log=log)
+            plan.sync()
+            out[g] = (plan.unpack(f)[0], log.cpu().numpy())
+        assert np.array_equal(out[False][0].view(np.uint64), out[True][0].view(np.uint64))
+        assert np.array_equal(out[False][1], out[True][1]) and np.all(out[True][1] > 0)
+        assert len(set(np.round(out[True][1], 12))) > 1
+        log = torch.from_numpy(out[True][1]).to(plan.device)
+        rep = {}
+        for g in (False, True):
+            plan = _plan(inst, "fp32_cn64", use_graph=g, stream=stream)
+            f = plan.pack(a0.astype(np.complex64))
+            plan.propagate(f, 40, dz_log=log, replay=True)
+            plan.sync()
+            rep[g] = plan.unpack(f)[0]
+        assert np.array_equal(rep[False].view(np.uint32), rep[True].view(np.uint32))
+        e = werr(rep[True].astype(np.complex128), out[True][0])
+        say(f"  graph plan replaying the adaptive log: {e:.2e} against FP64")
+        assert e < 1e-5
+
+
+@pytest.mark.parametrize("precision,nr,ipk", [("fp64", 40, 5e17), ("fp64", 64, 6e17), ("fp32_cn64", 64, 6e17)])
+def test_step_splitting_is_exact(precision, nr, ipk):
+    """step(n) then step(m) equals step(n+m) bitwise (state carried in the workspace; the fused
+    row pass hands each chunk's neighbour point the density its own thread uses, so two half
+    steps in one pass equal two passes bit for bit, also where the density is large)."""
+    inst = wl.config_full(nr=nr, nt=256)
+    a0 = wl.gaussian_field(inst) * math.sqrt(ipk / inst["I0"])
+    if precision != "fp64":
+        a0 = a0.astype(np.complex64)
+    view = np.uint64 if precision == "fp64" else np.uint32
+    p = _plan(inst, precision)
     f1 = p.pack(a0)
     p.step(f1, 7)
     p.sync()
-    q = _plan(inst, "fp64")
+    q = _plan(inst, precision)
     f2 = q.pack(a0)
     q.step(f2, 3)
     q.step(f2, 4)
     q.sync()
-    assert np.array_equal(p.unpack(f1)[0].view(np.uint64), q.unpack(f2)[0].view(np.uint64))
+    assert np.array_equal(p.unpack(f1)[0].view(view), q.unpack(f2)[0].view(view))
 
 
 def test_nonfinite_is_reported():
@@ -370,6 +410,28 @@ def test_nonfinite_is_reported():
         plan.sync()
     assert ei.value.code == fcn.FCN_E_NONFINITE
     plan.sync()  # the flag is cleared once reported
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_cn64"])
+def test_density_instability_is_reported(precision):
+    """A 30 fs spike above the RK4 density step's stability limit (1.99e18 W/m^2 on the
+    full-model time grid) is reported as FCN_E_UNSTABLE; the same spike at 1.9e18 W/m^2 is not
+    (the oracle shows the same limit on the CPU)."""
+    inst = wl.config_full(nr=16, nt=2048)
+    t = inst["t_min"] + np.arange(2048) * (inst["t_max"] - inst["t_min"]) / 2048
+    for ipk, stable in ((1.9e18, True), (2.1e18, False)):
+        a = np.zeros((16, 2048), dtype=complex)
+        a[:4] = np.sqrt(ipk * np.exp(-2 * (t / 30e-15) ** 2))
+        plan = _plan(inst, precision)
+        f = plan.pack(a if precision == "fp64" else a.astype(np.complex64))
+        plan.step(f, 1)
+        if stable:
+            plan.sync()
+        else:
+            with pytest.raises(fcn.FcnError) as ei:
+                plan.sync()
+            assert ei.value.code == fcn.FCN_E_UNSTABLE
+            plan.sync()  # both flags are cleared once reported
 
 
 def test_fp32_energy_drift_is_bounded():

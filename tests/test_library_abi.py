@@ -191,3 +191,4 @@ def test_network_abi_validates_on_host(lib):
     # the parareal combination validates its sizes on the host as well
     assert lib.fcn_parareal_update(p, p, p, p, p, 0, 16, p, 4, None) == fcn.FCN_E_ARG
     assert lib.fcn_parareal_update(p, p, p, p, p, 16, 16, p, 0, None) == fcn.FCN_E_ARG
+

@@ -190,6 +190,25 @@ fcn_status fcn_plan_destroy(fcn_plan_t plan);
 fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, double *row_ms, double *col_ms,
                           double *total_ms);
 
+/* Allocation-free variant of fcn_step, for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, tight serving loops, harnesses that forbid allocation).
+ * Instead of the caller-owned workspace of fcn_plan_bind it uses the library's own static
+ * device array of FCN_SCRATCH_BYTES bytes (one per GPU, held until the process ends; its
+ * address on the current device is looked up once per device).  The call uploads the plan's
+ * tables into that array on `stream` (hipStream_t cast to void*, NULL = default stream, of the
+ * current device) and waits for the upload, resets the step state there (step counter 0), then
+ * enqueues nsteps Strang steps on field_dev exactly as fcn_step does (same kernels, same
+ * results; no HIP graph) and returns without waiting for them.  The plan need not be bound; a
+ * bound plan keeps its own workspace, stream, step counter and graph untouched.
+ * Every call on one GPU shares that GPU's array and overwrites what the previous call left
+ * there: calls that overlap on one GPU (another stream or host thread) race and give wrong
+ * results.  A non-finite intensity is not reported (no fcn_sync for this call).
+ * Errors: FCN_E_SIZE if the plan needs more than FCN_SCRATCH_BYTES of workspace
+ * (fcn_plan_workspace_size); FCN_E_ARG for a NULL field or nsteps < 0; FCN_E_HIP.
+ * It calls no hipMalloc, hipFree or other allocating routine. */
+#define FCN_SCRATCH_BYTES (4u << 20)
+fcn_status fcn_step_scratch(fcn_plan_t plan, void *field_dev, int64_t nsteps, void *stream);
+
 /* Launch configuration the plan chose: frequencies per workgroup and rows per thread of the
  * column solve (of the last nr bucket), elements per thread of the row kernel for the
  * largest nt (8; 16 from nt = 4096, and from nt = 2048 with FP64 row arithmetic:

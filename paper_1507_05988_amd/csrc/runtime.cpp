@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -587,6 +588,38 @@ fcn_status run_steps(fcn_plan_t p, void *field, int64_t nsteps, double *diag, in
 
 }  // namespace
 
+namespace {
+
+// Device memory of fcn_step_scratch: one array per GPU, living until the process ends.  In
+// host code `scratch` is only a host-side handle of the symbol; its device address is looked
+// up per device with hipGetSymbolAddress and only that address is ever passed to kernels or
+// copies.
+static __device__ __align__(256) unsigned char scratch[FCN_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the static scratch on the current device, looked up once per device.
+fcn_status scratch_on_current_device(fcn_plan_t p, unsigned char **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(p, FCN_E_HIP, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(p, e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(p, FCN_E_HIP, "static scratch is not 256-byte aligned");
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return FCN_OK;
+}
+
+}  // namespace
+
 namespace fcn {
 // accessors for the library's other translation units (parareal driver)
 int plan_precision(fcn_plan_t p) { return p->precision; }
@@ -774,6 +807,46 @@ fcn_status fcn_sync(fcn_plan_t p) {
         return fail(p, FCN_E_NONFINITE, "non-finite intensity in the field");
     }
     return FCN_OK;
+}
+
+fcn_status fcn_step_scratch(fcn_plan_t p, void *field_dev, int64_t nsteps, void *stream) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    if (!field_dev) return fail(p, FCN_E_ARG, "field is NULL");
+    if (nsteps < 0) return fail(p, FCN_E_ARG, "nsteps < 0");
+    if (p->ws_bytes > FCN_SCRATCH_BYTES)
+        return fail(p, FCN_E_SIZE, "plan needs %zu bytes of workspace, the static scratch holds %u", p->ws_bytes,
+                    (unsigned)FCN_SCRATCH_BYTES);
+    unsigned char *scr = nullptr;
+    fcn_status st = scratch_on_current_device(p, &scr);
+    if (st != FCN_OK) return st;
+    // run on the scratch with a temporary binding; the plan's own binding is restored after
+    unsigned char *const ws0 = p->ws;
+    const hipStream_t stream0 = p->stream;
+    const bool bound0 = p->bound, seeded0 = p->seeded;
+    const int64_t n0 = p->n_host;
+    const int32_t graph0 = p->opt.use_graph;
+    p->ws = scr;
+    p->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(p->ws, p->image.data(), p->const_bytes, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = launch_init_state(p->d_state(), p->d_slots(), p->d_ring(), p->d_zpos(), p->batch, 0, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // the host image is read by the copy
+    if (e != hipSuccess) {
+        st = hip_fail(p, e, "upload plan tables to the static scratch");
+    } else {
+        p->bound = true;
+        p->n_host = 0;
+        p->seeded = false;
+        p->opt.use_graph = 0;  // a graph would hold this call's addresses
+        st = run_steps(p, field_dev, nsteps, nullptr, 0, nullptr, 0);
+    }
+    p->ws = ws0;
+    p->stream = stream0;
+    p->bound = bound0;
+    p->seeded = seeded0;
+    p->n_host = n0;
+    p->opt.use_graph = graph0;
+    return st;
 }
 
 fcn_status fcn_step_timed(fcn_plan_t p, void *field_dev, int64_t nsteps, double *row_ms, double *col_ms,

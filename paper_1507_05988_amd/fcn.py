@@ -29,8 +29,9 @@ EXPORTED = (
     "fcn_net_create", "fcn_net_param_count", "fcn_net_workspace_size", "fcn_net_bind", "fcn_net_refresh",
     "fcn_net_input", "fcn_net_forward", "fcn_net_target", "fcn_net_loss", "fcn_net_backward", "fcn_net_adam",
     "fcn_net_apply", "fcn_net_last_error", "fcn_net_destroy", "fcn_parareal_update",
-    "fcn_parareal_workspace_size", "fcn_parareal",
+    "fcn_parareal_workspace_size", "fcn_parareal", "fcn_step_scratch",
 )
+SCRATCH_BYTES = 4 << 20  # FCN_SCRATCH_BYTES
 PARAREAL_MAX_ITER = 64
 PARAREAL_STATUS = {0: "converged", 1: "diverging", 2: "nonfinite", 3: "kmax", 4: "fallback"}
 
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "fcn_diag_record_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
         "fcn_plan_bind": ([vp, vp, sz, vp], ctypes.c_int),
         "fcn_step": ([vp, vp, i64], ctypes.c_int),
+        "fcn_step_scratch": ([vp, vp, i64, vp], ctypes.c_int),
         "fcn_propagate": ([vp, vp, i64, vp, i32, vp, i32], ctypes.c_int),
         "fcn_diagnostics": ([vp, vp, vp], ctypes.c_int),
         "fcn_stage": ([vp, i32, vp, dbl], ctypes.c_int),
@@ -242,6 +244,13 @@ class Plan:
     # ---------------------------------------------------------------- entry points
     def step(self, field, nsteps: int):
         self._check(self.lib.fcn_step(self._h, self._field_ptr(field), int(nsteps)))
+
+    def step_scratch(self, field, nsteps: int, stream=None):
+        """fcn_step on the library's static device scratch instead of the plan's workspace
+        (the allocation-free entry point); enqueued on `stream` (default: the plan's)."""
+        s = self.stream if stream is None else stream
+        self._check(self.lib.fcn_step_scratch(self._h, self._field_ptr(field), int(nsteps),
+                                              ctypes.c_void_p(s.cuda_stream)))
 
     def propagate(self, field, nsteps: int, diag_every: int = 0, dz_log=None, replay: bool = False):
         """Steps and returns (diag tensor [records][diag_record] or None)."""

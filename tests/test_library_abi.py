@@ -192,3 +192,24 @@ def test_network_abi_validates_on_host(lib):
     assert lib.fcn_parareal_update(p, p, p, p, p, 0, 16, p, 4, None) == fcn.FCN_E_ARG
     assert lib.fcn_parareal_update(p, p, p, p, p, 16, 16, p, 0, None) == fcn.FCN_E_ARG
 
+
+def test_step_scratch_rejects_on_the_host(lib):
+    """fcn_step_scratch refuses, before any device call, a plan whose workspace exceeds the static
+    scratch, a NULL field and a negative step count."""
+    hdr = open(os.path.join(ROOT, "include", "fcn.h")).read()
+    m = re.search(r"#define FCN_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == fcn.SCRATCH_BYTES
+    insts = wl.config_batch(count=300)
+    rc, h = _create(lib, insts, precision=1)
+    assert rc == fcn.FCN_OK
+    sz = ctypes.c_size_t()
+    assert lib.fcn_plan_workspace_size(h, ctypes.byref(sz)) == 0
+    assert sz.value > fcn.SCRATCH_BYTES
+    assert lib.fcn_step_scratch(h, ctypes.c_void_p(0x1000), 1, None) == fcn.FCN_E_SIZE
+    assert b"static scratch" in lib.fcn_last_error(h)
+    assert lib.fcn_plan_destroy(h) == 0
+    rc, h = _create(lib, [wl.config_small(nr=16, nt=64)])
+    assert rc == fcn.FCN_OK
+    assert lib.fcn_step_scratch(h, None, 1, None) == fcn.FCN_E_ARG
+    assert lib.fcn_step_scratch(h, ctypes.c_void_p(0x1000), -1, None) == fcn.FCN_E_ARG
+    assert lib.fcn_plan_destroy(h) == 0

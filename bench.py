@@ -1,25 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the FCN z-step on one MI355X, in grid-point z-steps per second.
 
-Workload: the full-model pulse (Nr=512 over [0, 8 mm], Nt=2048 over [-400, 400) fs,
-w0 = 2 mm, tau = 100 fs, P = 5 Pcr, Kerr n2 + n4, 8-photon ionisation with plasma
-defocusing, multiphoton and collisional absorption, dz = 5 mm), in the FP32 field
-precision with FP64 density scan and diagnostics.  One step is one whole Strang z-step
-(column CN solve + fused iFFT / two nonlinear half steps / FFT row pass, diagnostics
-partials included) on the resident field.  The timed steps run in chunks of at most
-500 steps (z <= 2.5 m, before the collapse near 4.2 m), each chunk starting from the
-resident initial pulse: past the collapse the trajectory is chaotic and the explicit RK4
-density step can leave its stability region (sigma_K I^K dtau > 2.785).
-The line also carries the FP64 plain method, the FP32-storage mode (FP32 field, FP64
-arithmetic) and the FP32-CN64 mode (FP32 row pass with twiddle pairs, FP64 column solve) on
-the same workload, the errors of the three FP32-field modes against FP64 at
-checkpoints (with the FP64 run's own sensitivity to FP32 input rounding as the
-conditioning floor), parareal along z on a held-out learned-coarse trajectory (classical
-and learned coarse propagator, fine steps in FP32-CN64 and in FP32 storage, against the
-serial FP64 plain method), the long-distance
-pulse (1024 x 8192, adaptive dz) at checkpoints up to 10^4 steps (FP32 modes against FP64,
-FP64 against the CPU oracle's stored values; --long-pulse-checkpoints extends it), the
-roofline of the dominant kernel and the CPU oracle's rate on the host.
+Headline workload: the batched sweep -- 64 Kerr pulses of uneven grids in one plan (Nr in
+{256, 512, 1024}, Nt in {512, 1024, 2048, 4096}, P in [1, 10] Pcr, tau in [30, 200] fs, w0 in
+[0.5, 3] mm, seeded; 7.56e7 grid points, 605 MB as FP32 complex), advanced together one whole
+Strang z-step at a time (one row-kernel launch per distinct Nt: inverse FFT, two nonlinear half
+steps, diagnostics partials, FFT; one column-kernel launch per distinct Nr: the Crank-Nicholson
+solve) in the FP32-CN64 mode (FP32 field, FP32 FFTs with twiddle pairs and FP32 nonlinear step,
+FP64 column solve, FP64 diagnostics), replayed from captured HIP graphs of 16 steps, with the
+field resident in HBM.  Each instance steps with its own dz (1 cm or z_c/200); a run is 100
+steps, and longer timed runs restart from the resident initial pulses every 100 steps.
+The line also carries, on the same sweep, the FP64 plain method and plain FP32 with per-instance
+errors against FP64; per-launch kernel times with the roofline of the dominant kernel (HBM bytes
+and vector-ALU issue from the committed rocprofv3 counters); the full-model pulse (Nr=512,
+Nt=2048, plasma, MPA and collisions) in four precisions with errors at checkpoints; the paper's
+own grids; the long-distance pulse at checkpoints against the CPU oracle's stored values;
+parareal along z with the classical and the learned coarse propagator; the learned network's
+rates; and the CPU oracle's rate on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -36,6 +33,10 @@ import numpy as np
 
 METRIC = "grid-pt z-steps/s, FP32/parareal vs FP64 plain at 1e-5 rel err; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# Vector-ALU issue peak of one MI355X in lanes: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.  A
+# wave64 VALU instruction occupies a SIMD for 4 cycles (the build disables packed FP32, whose
+# dual issue is what the 157.3 TFLOP/s FP32 vector figure counts).
+VALU_PEAK_TLANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def weighted_rel_err(a, ref):
@@ -46,17 +47,41 @@ def weighted_rel_err(a, ref):
     return math.sqrt(np.sum(w[:, None] * np.abs(a - ref) ** 2) / np.sum(w[:, None] * np.abs(ref) ** 2))
 
 
-CHUNK = 500
+CHUNK = 500          # full-model pulse: timed chunks restart from z = 0 (before the collapse)
 ROOT = os.path.dirname(os.path.abspath(__file__))
+COUNTER_FILE = os.path.join(ROOT, "profiles", "fcn_step_batched64_counters.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fcn_step_fullmodel_512x2048_traffic.json")
+
+
+def _sources_hash(paths):
+    import hashlib
+
+    h = hashlib.sha256()
+    for src in paths:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_counters(precision, kernel_name):
+    """The committed rocprofv3 counters (HBM bytes per launch, copy-calibrated; VALU instructions
+    per launch) of one kernel of the batched sweep, or None when no run covers it or its sources
+    changed since."""
+    try:
+        with open(COUNTER_FILE) as fh:
+            entries = json.load(fh)["kernels"]
+        for t in entries:
+            if t["precision"] == precision and t["kernel"] == kernel_name:
+                return t if _sources_hash(t["sources"]) == t["sources_sha256"] else None
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
 
 
 def measured_traffic(precision, kernel, tiles):
     """HBM bytes per launch of one kernel of the full-model step (`kernel` "row" or "col") in
     `precision` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or
     None when no run covers that kernel or its sources changed since."""
-    import hashlib
-
     try:
         with open(TRAFFIC_FILE) as fh:
             entries = json.load(fh)["kernels"]
@@ -65,25 +90,22 @@ def measured_traffic(precision, kernel, tiles):
                 continue
             if kernel == "col" and [t["col_tile"], t["col_rows"]] != [tiles["col_tile"], tiles["col_rows"]]:
                 continue
-            h = hashlib.sha256()
-            for src in t["sources"]:
-                with open(os.path.join(ROOT, src), "rb") as fh:
-                    h.update(fh.read())
-            return int(t["bytes_per_launch"]) if h.hexdigest() == t["sources_sha256"] else None
+            return int(t["bytes_per_launch"]) if _sources_hash(t["sources"]) == t["sources_sha256"] else None
     except (OSError, KeyError, ValueError):
         pass
     return None
 
 
-def timed_steps(plan, field, init, steps, torch):
-    """`steps` steps in chunks of CHUNK, each chunk restarting from the resident initial
-    field `init`; every chunk is bracketed by device synchronisation and timed with events
-    on the plan's stream (the restart copies are outside the timed intervals).  Seconds."""
+def timed_steps(plan, field, init, steps, torch, chunk=CHUNK):
+    """`steps` steps in chunks of `chunk`, each chunk restarting from the resident initial field
+    `init`; every chunk is bracketed by device synchronisation and timed with events on the
+    plan's stream (the restart copies are outside the timed intervals).  Seconds."""
     total = 0.0
     done = 0
     while done < steps:
-        n = min(CHUNK, steps - done)
-        field.copy_(init)
+        n = min(chunk, steps - done)
+        with torch.cuda.stream(plan.stream):
+            field.copy_(init)
         torch.cuda.synchronize()
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
@@ -114,35 +136,32 @@ def copy_bandwidth(torch):
     return round(nbytes / best / 1e9, 1)
 
 
-def cpu_baseline(inst, a0, seconds: float):
-    """The FP64 oracle on the host cores over a bounded sample of the same workload."""
+def cpu_baseline(insts, seconds: float):
+    """The FP64 oracle on the host cores over a bounded sample of the headline workload: whole
+    sweep steps (every instance one step from its initial pulse, then the next step ...), as many
+    as fit in about `seconds`; plus the oracle on the paper's timing grid (Sec. 5.1, Table 2) on
+    one thread and on all threads, as CPU context."""
     import oracle
-
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    pts = int(inst["nr"]) * int(inst["nt"])
-    t0 = time.perf_counter()
-    a = oracle.propagate(inst, a0, 1, threads=threads)
-    t1 = time.perf_counter() - t0
-    n = max(1, min(2000, int(seconds / max(t1, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.propagate(inst, a, n, threads=threads)
-    dt = time.perf_counter() - t0
-    out = {"value": pts * n / dt, "unit": "grid-pt z-steps/s", "cores": threads, "kind": "oracle",
-           "sample": f"{n} FP64 oracle steps of the {inst['nr']}x{inst['nt']} full-model pulse "
-                     f"(after 1 warm step), {dt:.1f} s"}
-    # the same oracle on one thread (a few steps), and on the grid of the paper's timing
-    # example (Nr = 2112, Nt = 2048, Sec. 5.1 Table 2) on one thread and on all threads
     from paper_1507_05988_amd import workloads as wl
 
-    n1 = max(1, int(min(seconds / 4, 5.0) / max(t1 * threads, 1e-6)))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    fields = [wl.gaussian_field(i) for i in insts]
+    pts = wl.points(insts)
     t0 = time.perf_counter()
-    oracle.propagate(inst, a, n1, threads=1)
-    d1 = time.perf_counter() - t0
-    out["one_thread"] = {"value": pts * n1 / d1, "steps": n1, "seconds": round(d1, 2)}
+    fields = [oracle.propagate(i, a, 1, threads=threads) for i, a in zip(insts, fields)]
+    t1 = time.perf_counter() - t0
+    n = max(1, min(100, int(seconds / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        fields = [oracle.propagate(i, a, 1, threads=threads) for i, a in zip(insts, fields)]
+    dt = time.perf_counter() - t0
+    out = {"value": pts * n / dt, "unit": "grid-pt z-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} FP64 oracle z-steps of all {len(insts)} pulses of the batched sweep "
+                     f"({pts} points; after 1 warm step), {dt:.1f} s"}
     pg = wl.config_paper_timing()
     ag = wl.gaussian_field(pg)
     rec = {"grid": f"{pg['nr']}x{pg['nt']}"}
-    for label, th, steps in (("all_threads", threads, 5), ("one_thread", 1, 1)):
+    for label, th, steps in (("all_threads", threads, 3), ("one_thread", 1, 1)):
         t0 = time.perf_counter()
         oracle.propagate(pg, ag, steps, threads=th)
         d = time.perf_counter() - t0
@@ -151,57 +170,90 @@ def cpu_baseline(inst, a0, seconds: float):
     return out
 
 
-def batched_sweep_measurement(torch):
-    """The 64-pulse ragged sweep (Nr in {256, 512, 1024}, Nt in {512 ... 4096}, about 7.5e7
-    points, Kerr, one plan with autotuned column tiles), 100 steps, in FP64, FP32 and
-    FP32-CN64: aggregate throughput, per-pass kernel times (kernel-own events; one launch per
-    distinct Nt or Nr) and the largest per-instance field error against the FP64 GPU run."""
-    from paper_1507_05988_amd import autotune, fcn
+def kernel_name(precision, launch, tiles):
+    """Template name of one launch of the sweep's step, as rocprofv3 reports it."""
+    if launch["pass"] == "row":
+        nt = launch["size"]
+        e = 16 if nt >= 4096 or (precision in ("fp64", "fp32_storage") and nt >= 2048) else 8
+        r = "double" if precision in ("fp64", "fp32_storage") else "float"
+        st = "double" if precision == "fp64" else "float"
+        flags = 63 + (256 if precision == "fp32_cn64" else 0)  # iFFT, NL, diagnostics, NL, FFT, store
+        return f"row_kernel<{r}, {st}, {nt}, {e}, {flags}>"
+    r = "float" if precision == "fp32" else "double"
+    st = "double" if precision == "fp64" else "float"
+    return f"col_kernel<{r}, {st}, {tiles[0]}, {tiles[1]}>"
+
+
+def sweep_run(torch, insts, precision, steps, warmup, tiles, graph=True):
+    """One plan over the whole sweep on its own stream: `steps` timed steps (graph replay), then
+    per-launch kernel times, then the field after one 100-step run.  Returns (seconds, launches,
+    fields, plan tiles)."""
+    from paper_1507_05988_amd import fcn
     from paper_1507_05988_amd import workloads as wl
 
-    insts = wl.config_batch()
-    pts = sum(int(i["nr"]) * int(i["nt"]) for i in insts)
-    byt = pts * 16
-    t64 = autotune.tune(insts, "fp64", steps=10, repeats=2)
-    p64 = fcn.Plan(insts, precision="fp64", col_tile=t64["col_tile"], col_rows=t64["col_rows"])
-    init64 = p64.pack([wl.gaussian_field(i) for i in insts])
-    f64 = init64.clone()
-    p64.step(f64, 5)
-    sec64 = timed_steps(p64, f64, init64, wl.BATCH_STEPS, torch)
-    f64.copy_(init64)
-    p64.step(f64, wl.BATCH_STEPS)
-    p64.sync()
-    ref = p64.unpack(f64)
-    del p64, f64, init64
-    out = {"points": pts, "instances": len(insts), "steps": wl.BATCH_STEPS, "unit": "grid-pt z-steps/s",
-           "fp64_plain": {"value": round(pts * wl.BATCH_STEPS / sec64, 1),
-                          "ms_per_step": round(sec64 * 1e3 / wl.BATCH_STEPS, 4),
-                          "col_tile": [t64["col_tile"], t64["col_rows"]]}}
-    for prec in ("fp32", "fp32_cn64"):
-        t = autotune.tune(insts, prec, steps=10, repeats=2)
-        plan = fcn.Plan(insts, precision=prec, col_tile=t["col_tile"], col_rows=t["col_rows"])
-        init = plan.pack([wl.gaussian_field(i, np.complex64) for i in insts])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = fcn.Plan(insts, precision=precision, use_graph=graph, stream=stream, col_tile=tiles[0],
+                        col_rows=tiles[1])
+        dt = np.complex128 if precision == "fp64" else np.complex64
+        init = plan.pack([wl.gaussian_field(i, dt) for i in insts])
         f = init.clone()
-        plan.step(f, 5)
-        sec = timed_steps(plan, f, init, wl.BATCH_STEPS, torch)
+        if warmup > 0:
+            plan.step(f, min(warmup, wl.BATCH_STEPS))
+        sec = timed_steps(plan, f, init, steps, torch, chunk=wl.BATCH_STEPS)
         f.copy_(init)
-        krow, kcol, _ = plan.step_timed(f, 20)
+        launches = plan.step_timed_launches(f, 20)
         f.copy_(init)
         plan.step(f, wl.BATCH_STEPS)
         plan.sync()
-        errs = [weighted_rel_err(g.astype(np.complex128), r) for g, r in zip(plan.unpack(f), ref)]
-        value = pts * wl.BATCH_STEPS / sec
-        out[prec] = {
-            "value": round(value, 1), "ms_per_step": round(sec * 1e3 / wl.BATCH_STEPS, 4),
-            "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1), "row_pass_ms": round(krow, 4),
-            "col_pass_ms": round(kcol, 4), "col_tile": [t["col_tile"], t["col_rows"]],
-            "field_error_vs_fp64_max": max(errs), "field_error_vs_fp64_median": float(np.median(errs)),
-            "vs_fp64_plain": round(sec64 / sec, 3),
-            "roofline_row_pass": {"bound": "hbm", "achieved": round(byt / (krow * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                                  "unit": "GB/s", "frac": round(byt / (krow * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-            "roofline_col_pass": {"bound": "hbm", "achieved": round(byt / (kcol * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                                  "unit": "GB/s", "frac": round(byt / (kcol * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
-        del plan, f, init
+        fields = plan.unpack(f)
+        diags = plan.split_diag(plan.diagnostics(f))
+        used = plan.tiles()[:2]
+        plan.close()
+        del f, init
+    return sec, launches, fields, diags, used
+
+
+def sweep_measurement(torch, args):
+    """The headline: the 64-pulse sweep in `args.headline_precision`, graph-replayed; FP64 plain
+    and the other FP32 mode beside it; per-instance errors against FP64 after one 100-step run."""
+    from paper_1507_05988_amd import autotune
+    from paper_1507_05988_amd import workloads as wl
+
+    insts = wl.config_batch()
+    pts = wl.points(insts)
+    hp = args.headline_precision
+    modes = [hp] if args.only_headline else [hp, "fp64", "fp32" if hp == "fp32_cn64" else "fp32_cn64"]
+    res = {}
+    for prec in modes:
+        t = autotune.tune(insts, prec, steps=10, repeats=2)
+        tiles = (t["col_tile"], t["col_rows"])
+        steps = args.steps if prec == hp else wl.BATCH_STEPS
+        sec, launches, fields, diags, used = sweep_run(torch, insts, prec, steps, args.warmup, tiles)
+        res[prec] = dict(sec=sec, steps=steps, launches=launches, fields=fields, diags=diags, tiles=used,
+                         table=t["table"])
+        print(f"[bench] sweep {prec}: {steps} steps in {sec:.4f} s ({sec / steps * 1e3:.3f} ms/step), "
+              f"column tile {used[0]}x{used[1]}", file=sys.stderr, flush=True)
+    return insts, pts, res
+
+
+def sweep_errors(insts, got, ref, dgot, dref):
+    """Per-instance errors of a sweep run against the FP64 one: r-weighted field error, largest
+    element error relative to the largest element, fluence and energy."""
+    rows = []
+    for i, (g, r, dg, dr) in enumerate(zip(got, ref, dgot, dref)):
+        g = g.astype(np.complex128)
+        rows.append({"field": weighted_rel_err(g, r),
+                     "elementwise": float(np.max(np.abs(g - r)) / np.max(np.abs(r))),
+                     "fluence": float(np.max(np.abs(dg["fluence"] - dr["fluence"])) / np.max(dr["fluence"])),
+                     "energy": abs(dg["energy"] / dr["energy"] - 1)})
+    out = {}
+    for k in ("field", "elementwise", "fluence", "energy"):
+        v = [r[k] for r in rows]
+        out[k + "_max"] = max(v)
+        out[k + "_median"] = float(np.median(v))
+    worst = int(np.argmax([r["field"] for r in rows]))
+    out["worst_instance"] = {"index": worst, "grid": f"{insts[worst]['nr']}x{insts[worst]['nt']}"}
     return out
 
 
@@ -388,7 +440,8 @@ def coarse_net_measurement(torch):
 def parareal_measurement(torch, precision="fp32_cn64"):
     """Parareal along z for held-out learned-coarse trajectory 2000 (Nr=512, Nt=2048, Kerr only,
     never used in training), fine and coarse FCN steps in `precision`, against the serial
-    FP64 plain method over the same steps (device time):
+    FP64 plain method and the serial fine solver in `precision` over the same steps (device time;
+    on one GPU a parareal iteration redoes the whole serial fine work, batched over the windows):
       * the parareal workload as specified, 32 windows x 50 steps of 0.2 mm, classical coarse
         step (one FCN step per window);
       * the learned-coarse variant, 8 windows x 250 steps, classical and learned coarse step
@@ -424,7 +477,22 @@ def parareal_measurement(torch, precision="fp32_cn64"):
         e1.record(p64.stream)
         torch.cuda.synchronize()
         t64 = e0.elapsed_time(e1) * 1e-3
-        out = {"fp64_plain_serial": {"seconds": round(t64, 6), "value": round(work / t64, 1)}}
+        # the serial fine solver in the fine precision of parareal: the same-precision comparison
+        ps = fcn.Plan(inst, precision=precision)
+        fs = ps.pack(a0.astype(np.complex64))
+        ps.step(fs, 2)
+        fs = ps.pack(a0.astype(np.complex64))
+        torch.cuda.synchronize()
+        e0.record(ps.stream)
+        ps.step(fs, nwin * spw)
+        e1.record(ps.stream)
+        torch.cuda.synchronize()
+        tfine = e0.elapsed_time(e1) * 1e-3
+        efine = weighted_rel_err(ps.unpack(fs)[0].astype(np.complex128), p64.unpack(ref[-1])[0])
+        del ps, fs
+        out = {"fp64_plain_serial": {"seconds": round(t64, 6), "value": round(work / t64, 1)},
+               "serial_fine_same_precision": {"seconds": round(tfine, 6), "value": round(work / tfine, 1),
+                                              "error_vs_fp64": efine}}
         variants = [("classical", None)]
         if learned and net is not None:
             variants.append(("learned", net))
@@ -439,6 +507,7 @@ def parareal_measurement(torch, precision="fp32_cn64"):
             _, nat = coarse.parareal_native(inst, params, **kw)
             tp = nat["seconds"]
             out[name] = {"seconds": round(tp, 6), "value": round(work / tp, 1), "vs_fp64_plain": round(t64 / tp, 3),
+                         "vs_serial_fine_same_precision": round(tfine / tp, 3),
                          "iterations": [{"k": h["iter"], "error": h["error"],
                                          "change": h["change"] if h["iter"] else None} for h in hist],
                          "status": hist[-1].get("status"), "final_error": hist[-1]["error"],
@@ -449,22 +518,102 @@ def parareal_measurement(torch, precision="fp32_cn64"):
     return res
 
 
+def full_model_measurement(torch, args):
+    """The full-model pulse (Nr=512, Nt=2048, Kerr n2+n4, plasma, MPA and collisions, dz = 5 mm)
+    in FP32-CN64, plain FP32, FP32 storage and FP64, timed in chunks of 500 steps from z = 0
+    (before the collapse near 4.2 m; past it the explicit RK4 density step can leave its
+    stability region, which the library reports as FCN_E_UNSTABLE); per-kernel times; errors of
+    the FP32-field modes against FP64 at checkpoints, with the FP64 run's own sensitivity to FP32
+    input rounding as the conditioning floor."""
+    from paper_1507_05988_amd import autotune, fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    inst = wl.config_full()
+    pts = int(inst["nr"]) * int(inst["nt"])
+    a0 = wl.gaussian_field(inst)
+    n = min(max(args.steps, 100), 1000)
+    out = {"grid": "512x2048", "steps": n, "unit": "grid-pt z-steps/s"}
+    for prec in ("fp32_cn64", "fp32", "fp32_storage", "fp64"):
+        t = autotune.tune(inst, prec, steps=50, repeats=3)
+        plan = fcn.Plan(inst, precision=prec, col_tile=t["col_tile"], col_rows=t["col_rows"])
+        init = plan.pack(a0 if prec == "fp64" else a0.astype(np.complex64))
+        f = init.clone()
+        plan.step(f, 20)
+        sec = timed_steps(plan, f, init, n, torch)
+        plan.sync()
+        f.copy_(init)
+        krow, kcol, _ = plan.step_timed(f, min(n, CHUNK))
+        plan.sync()
+        byt = 64 if prec == "fp64" else 32
+        out[prec] = {"value": round(pts * n / sec, 1), "ms_per_step": round(sec * 1e3 / n, 6),
+                     "row_ms": round(krow, 6), "col_ms": round(kcol, 6),
+                     "hbm_gbs_algorithmic": round(pts * n / sec * byt / 1e9, 1),
+                     "col_tile": [t["col_tile"], t["col_rows"]],
+                     "traffic_row": measured_traffic(prec, "row", t), "traffic_col": measured_traffic(prec, "col", t)}
+        del plan, f, init
+    for prec in ("fp32_cn64", "fp32", "fp32_storage"):
+        out[prec]["vs_fp64_plain"] = round(out[prec]["value"] / out["fp64"]["value"], 3)
+    if args.no_accuracy:
+        return out
+    checkpoints = (250, 500, 750, 1000, wl.FULL_STEPS)
+    runs = {"fp64": fcn.Plan(inst, precision="fp64"), "floor": fcn.Plan(inst, precision="fp64"),
+            "fp32": fcn.Plan(inst, precision="fp32"), "fp32_storage": fcn.Plan(inst, precision="fp32_storage"),
+            "fp32_cn64": fcn.Plan(inst, precision="fp32_cn64")}
+    a32 = a0.astype(np.complex64)
+    g = {k: p.pack(a0 if k == "fp64" else (a32.astype(np.complex128) if k == "floor" else a32))
+         for k, p in runs.items()}
+    alive = {k: True for k in runs}
+    acc = []
+    done = 0
+    for cp in checkpoints:
+        for k, p in runs.items():
+            if not alive[k]:
+                continue
+            p.step(g[k], cp - done)
+            try:
+                p.sync()
+            except fcn.FcnError as e:
+                alive[k] = f"stopped before step {cp}: {e}"
+        done = cp
+        x64 = runs["fp64"].unpack(g["fp64"])[0]
+        d64 = runs["fp64"].split_diag(runs["fp64"].diagnostics(g["fp64"]))[0]
+        row = {"steps": cp, "z_m": round(cp * inst["dz"], 4), "i_max_fp64": d64["i_max"],
+               "rho_max_fp64": d64["rho_max"],
+               "floor_fp64_from_fp32_input": weighted_rel_err(runs["floor"].unpack(g["floor"])[0], x64)}
+        for k in ("fp32", "fp32_storage", "fp32_cn64"):
+            if alive[k] is not True:
+                row[k] = alive[k]
+                continue
+            p = runs[k]
+            x = p.unpack(g[k])[0].astype(np.complex128)
+            d = p.split_diag(p.diagnostics(g[k]))[0]
+            row[k] = {"field": weighted_rel_err(x, x64),
+                      "elementwise": float(np.max(np.abs(x - x64)) / np.max(np.abs(x64))),
+                      "fluence": float(np.max(np.abs(d["fluence"] - d64["fluence"])) / np.max(d64["fluence"])),
+                      "rho_max": abs(d["rho_max"] - d64["rho_max"]) / max(d64["rho_max"], 1e-300),
+                      "energy": abs(d["energy"] / d64["energy"] - 1)}
+        acc.append(row)
+    out["accuracy_vs_fp64"] = acc
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--headline-precision", default="fp32_cn64", choices=["fp32_cn64", "fp32"],
+                    help="mode of the headline line: fp32_cn64 (within 1e-5 of FP64 on every pulse of the "
+                         "sweep) or fp32 (faster; its largest pulse misses 1e-5)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the headline sweep in the headline mode (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-full-model", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--no-net", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-paper-shapes", action="store_true")
-    ap.add_argument("--headline-precision", default="fp32_cn64", choices=["fp32_cn64", "fp32"],
-                    help="mode of the headline line: fp32_cn64 (within 1e-5 of FP64 over the timed "
-                         "chunks) or fp32 (faster, within 1e-5 for about 190 steps of this workload)")
     ap.add_argument("--no-long-pulse", action="store_true")
     ap.add_argument("--long-pulse-checkpoints", default="100,1000,10000",
                     help="comma-separated step counts of the long-distance pulse checkpoints")
@@ -484,8 +633,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1507_05988_amd import fcn
-    from paper_1507_05988_amd import workloads as wl
 
     if args.only_net:
         print(json.dumps({"coarse_net": coarse_net_measurement(torch)}), flush=True)
@@ -500,47 +647,36 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "reps": 10}))
         return
 
-    inst = wl.config_full()
-    pts = int(inst["nr"]) * int(inst["nt"])
-    a0 = wl.gaussian_field(inst)
-
-    # ---- FP32 timed region
-    from paper_1507_05988_amd import autotune
-
-    tiles = {prec: autotune.tune(inst, prec, steps=50, repeats=3) for prec in ("fp32", "fp64", "fp32_storage", "fp32_cn64")}
-    tile_kw = {prec: dict(col_tile=t["col_tile"], col_rows=t["col_rows"]) for prec, t in tiles.items()}
-    print("[bench] column tiles (autotuned): " + ", ".join(f"{k} {t['col_tile']}x{t['col_rows']}" for k, t in tiles.items()),
-          file=sys.stderr, flush=True)
+    insts, pts, sw = sweep_measurement(torch, args)
     hp = args.headline_precision
-    p32 = fcn.Plan(inst, precision=hp, **tile_kw[hp])
-    init32 = p32.pack(a0.astype(np.complex64))
-    f32 = init32.clone()
-    if args.warmup > 0:
-        p32.step(f32, min(args.warmup, CHUNK))
-    sec = timed_steps(p32, f32, init32, args.steps, torch)
-    p32.sync()
-    value = pts * args.steps / sec
-    ms_per_step = sec * 1e3 / args.steps
-    print(f"[bench] {hp} {args.steps} steps in {sec:.4f} s ({ms_per_step * 1e3:.2f} us/step)", file=sys.stderr,
-          flush=True)
+    h = sw[hp]
+    value = pts * h["steps"] / h["sec"]
+    ms_per_step = h["sec"] * 1e3 / h["steps"]
 
-    # ---- per-kernel durations with HIP events on the plan's stream
-    f32.copy_(init32)
-    krow, kcol, _ = p32.step_timed(f32, min(args.steps, CHUNK))
-    p32.sync()
-    bytes_per_launch = pts * 2 * 8  # each pass reads and writes every FP32 complex value once
-    row_name = ("row_kernel<float, float, 2048, 8> (iFFT + 2 NL half steps + FFT"
-                + (", twiddle pairs)" if hp == "fp32_cn64" else ")"))
-    col_name = (f"col_kernel<{'double' if hp == 'fp32_cn64' else 'float'}, float, {tiles[hp]['col_tile']}, "
-                f"{tiles[hp]['col_rows']}> (CN solve)")
-    dom = "row" if krow >= kcol else "col"
-    dom_name, dom_ms = (row_name, krow) if dom == "row" else (col_name, kcol)
-    achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(hp, dom, tiles[hp]),
-                "kernel": dom_name, "kernel_ms": round(dom_ms, 6), "row_ms": round(krow, 6), "col_ms": round(kcol, 6),
-                "bytes_per_launch": bytes_per_launch}
-    print(f"[bench] kernel means: row {krow * 1e3:.2f} us, col {kcol * 1e3:.2f} us", file=sys.stderr, flush=True)
+    # ---- roofline of the dominant kernel: the launch of the step with the longest mean duration
+    launches = h["launches"]
+    for L in launches:
+        L["kernel"] = kernel_name(hp, L, h["tiles"])
+        L["bytes"] = L["points"] * 16  # FP32 field: each launch reads and writes its points once
+        L["gbs"] = round(L["bytes"] / (L["ms"] * 1e-3) / 1e9, 1)
+    dom = max(launches, key=lambda L: L["ms"])
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    cnt = measured_counters(hp, dom["kernel"])
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": int(cnt["bytes_per_launch"]) if cnt else None}
+    roofline = dict(hbm)
+    if cnt and cnt.get("valu_insts_per_launch"):
+        lane_ops = cnt["valu_insts_per_launch"] * 64 / (dom["ms"] * 1e-3) / 1e12
+        valu = {"bound": "alu", "achieved": round(lane_ops, 3), "peak": round(VALU_PEAK_TLANE_OPS, 3),
+                "unit": "T VALU lane-ops/s", "frac": round(lane_ops / VALU_PEAK_TLANE_OPS, 4),
+                "valu_insts_per_launch": cnt["valu_insts_per_launch"]}
+        if valu["frac"] > hbm["frac"]:
+            roofline = dict(valu, traffic=hbm["traffic"], hbm=hbm)
+        else:
+            roofline["valu"] = valu
+    roofline.update(kernel=dom["kernel"], kernel_ms=round(dom["ms"], 6), points_per_launch=dom["points"],
+                    bytes_per_launch=dom["bytes"])
 
     out = {
         "metric": METRIC,
@@ -555,126 +691,62 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if hp == "fp32_cn64" else "f32",
         "data": "synthetic",
-        "config": {"workload": ("full-model pulse, FP32 field, FP32 FFTs (twiddle pairs) and nonlinear step, "
-                                "FP64 CN column solve and density scan" if hp == "fp32_cn64" else
-                                "full-model pulse, FP32 field / FP64 density") +
-                               f", Nr=512, Nt=2048, dz=5 mm, timed in chunks of {CHUNK} steps from z=0",
-                   "precision": hp,
-                   "nr": int(inst["nr"]), "nt": int(inst["nt"]), "dz": inst["dz"], "P_over_Pcr": 5.0,
-                   "terms": "diffraction+GVD+Kerr(n2,n4)+plasma+MPA(K=8)+collisions"},
+        "config": {"workload": ("batched sweep: 64 Kerr pulses of uneven grids (Nr 256-1024, Nt 512-4096, "
+                                "7.56e7 points) advanced together, one Strang z-step per step, "
+                                + ("FP32 field, FP32 FFTs (twiddle pairs) and nonlinear step, FP64 CN column "
+                                   "solve and diagnostics" if hp == "fp32_cn64" else "FP32 field and arithmetic, "
+                                   "FP64 diagnostics")
+                                + f", HIP-graph replay, timed in runs of {wl_batch_steps()} steps from the "
+                                  "initial pulses"),
+                   "precision": hp, "instances": len(insts), "points": pts,
+                   "column_tile": list(h["tiles"]), "terms": "diffraction+GVD+Kerr(n2)"},
         "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1),
         "roofline": roofline,
+        "launches": [{k: (round(v, 6) if k == "ms" else v) for k, v in L.items()} for L in launches],
         "hbm_copy_gbs": copy_bandwidth(torch),
-        "column_tiles": {k: {"col_tile": t["col_tile"], "col_rows": t["col_rows"],
-                             "col_us": {kk: round(v * 1e3, 2) for kk, v in t["table"].items()}} for k, t in tiles.items()},
     }
-
-    # ---- FP64 plain method on the same workload
-    if not args.no_fp64:
-        p64 = fcn.Plan(inst, precision="fp64", **tile_kw["fp64"])
-        init64 = p64.pack(a0)
-        f64 = init64.clone()
-        p64.step(f64, min(args.warmup, 50) or 1)
-        n64 = min(args.steps, 1000)
-        s64 = timed_steps(p64, f64, init64, n64, torch)
-        p64.sync()
-        f64.copy_(init64)
-        r64, c64, _ = p64.step_timed(f64, min(n64, CHUNK))
-        out["fp64_plain"] = {"value": round(pts * n64 / s64, 1), "ms_per_step": round(s64 * 1e3 / n64, 6),
-                             "steps": n64, "row_ms": round(r64, 6), "col_ms": round(c64, 6),
-                             "hbm_gbs_algorithmic": round(pts * n64 / s64 * 64 / 1e9, 1)}
-        del p64, f64
-        out["vs_fp64_plain"] = round(value / (pts * n64 / s64), 3)
-        for mode in ("fp32_storage", "fp32_cn64" if hp == "fp32" else "fp32"):
-            pm = fcn.Plan(inst, precision=mode, **tile_kw[mode])
-            initm = pm.pack(a0.astype(np.complex64))
-            fm = initm.clone()
-            pm.step(fm, min(args.warmup, 50) or 1)
-            sm = timed_steps(pm, fm, initm, n64, torch)
-            pm.sync()
-            fm.copy_(initm)
-            rm, cm, _ = pm.step_timed(fm, min(n64, CHUNK))
-            out[mode] = {"value": round(pts * n64 / sm, 1), "ms_per_step": round(sm * 1e3 / n64, 6),
-                         "steps": n64, "row_ms": round(rm, 6), "col_ms": round(cm, 6),
-                         "hbm_gbs_algorithmic": round(pts * n64 / sm * 32 / 1e9, 1),
-                         "vs_fp64_plain": round(s64 / sm, 3)}
-            del pm, fm
-
-    # ---- FP32 error against the FP64 GPU method at checkpoints; the FP64 run started from
-    # the FP32-rounded input measures how much the trajectory itself amplifies FP32 rounding
-    if not args.no_accuracy:
-        checkpoints = (250, 500, 750, 1000, wl.FULL_STEPS)
-        q32 = fcn.Plan(inst, precision="fp32")
-        q64 = fcn.Plan(inst, precision="fp64")
-        qr = fcn.Plan(inst, precision="fp64")
-        qm = fcn.Plan(inst, precision="fp32_storage")
-        qc = fcn.Plan(inst, precision="fp32_cn64")
-        gc = qc.pack(a0.astype(np.complex64))
-        ok_c = True
-        g32 = q32.pack(a0.astype(np.complex64))
-        g64 = q64.pack(a0)
-        gr = qr.pack(a0.astype(np.complex64).astype(np.complex128))
-        gm = qm.pack(a0.astype(np.complex64))
-        ok_m = True
-        acc = []
-        done = 0
-        for cp in checkpoints:
-            for q, g in ((q32, g32), (q64, g64), (qr, gr), (qm, gm), (qc, gc)):
-                q.step(g, cp - done)
-            done = cp
-            ok32 = True
-            try:
-                q32.sync()
-            except fcn.FcnError:
-                ok32 = False
-            q64.sync()
-            qr.sync()
-            try:
-                qm.sync()
-            except fcn.FcnError:
-                ok_m = False
-            try:
-                qc.sync()
-            except fcn.FcnError:
-                ok_c = False
-            x64 = q64.unpack(g64)[0]
-            d32 = q32.split_diag(q32.diagnostics(g32))[0]
-            d64 = q64.split_diag(q64.diagnostics(g64))[0]
-            row = {"steps": cp, "z_m": round(cp * inst["dz"], 4),
-                   "floor_fp64_from_fp32_input": weighted_rel_err(qr.unpack(gr)[0], x64),
-                   "i_max_fp64": d64["i_max"], "rho_max_fp64": d64["rho_max"]}
-            if ok32:
-                x32 = q32.unpack(g32)[0].astype(np.complex128)
-                row.update(field=weighted_rel_err(x32, x64),
-                           fluence=float(np.max(np.abs(d32["fluence"] - d64["fluence"])) / np.max(d64["fluence"])),
-                           rho_max=abs(d32["rho_max"] - d64["rho_max"]) / max(d64["rho_max"], 1e-300),
-                           energy=abs(d32["energy"] / d64["energy"] - 1))
-            else:
-                row.update(field=None, note="FP32 trajectory left the RK4 density stability region")
-            row["field_fp32_storage"] = weighted_rel_err(qm.unpack(gm)[0].astype(np.complex128), x64) if ok_m else None
-            row["field_fp32_cn64"] = weighted_rel_err(qc.unpack(gc)[0].astype(np.complex128), x64) if ok_c else None
-            acc.append(row)
-            if not ok32:
-                break
-        out["accuracy_fp32_vs_fp64"] = acc
-
-    if not args.no_batch:
-        out["batched_sweep"] = batched_sweep_measurement(torch)
-    if not args.no_paper_shapes:
-        out["paper_shapes"] = paper_shapes_measurement(torch)
-    if not args.no_long_pulse:
-        out["long_pulse"] = long_pulse_measurement(torch, [int(x) for x in args.long_pulse_checkpoints.split(",")])
-    if not args.no_parareal:
-        # fine and coarse steps in FP32-CN64 (parareal target 1e-4), and in FP32 storage (1e-5)
-        out["parareal"] = parareal_measurement(torch, "fp32_cn64")
-        out["parareal_fp32_storage"] = parareal_measurement(torch, "fp32_storage")
-    if not args.no_net:
-        out["coarse_net"] = coarse_net_measurement(torch)
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, a0, args.cpu_seconds)
+    if "fp64" in sw:
+        ref, dref = sw["fp64"]["fields"], sw["fp64"]["diags"]
+        v64 = pts * sw["fp64"]["steps"] / sw["fp64"]["sec"]
+        out["vs_fp64_plain"] = round(value / v64, 3)
+        out["accuracy_vs_fp64"] = sweep_errors(insts, h["fields"], ref, h["diags"], dref)
+        out["sweep"] = {"fp64_plain": {"value": round(v64, 1), "ms_per_step": round(sw["fp64"]["sec"] * 1e3 /
+                                                                                   sw["fp64"]["steps"], 4),
+                                       "column_tile": list(sw["fp64"]["tiles"]),
+                                       "launches": [{"pass": L["pass"], "size": L["size"], "ms": round(L["ms"], 6)}
+                                                    for L in sw["fp64"]["launches"]]}}
+        for k, r in sw.items():
+            if k in (hp, "fp64"):
+                continue
+            v = pts * r["steps"] / r["sec"]
+            out["sweep"][k] = {"value": round(v, 1), "ms_per_step": round(r["sec"] * 1e3 / r["steps"], 4),
+                               "vs_fp64_plain": round(v / v64, 3), "column_tile": list(r["tiles"]),
+                               "launches": [{"pass": L["pass"], "size": L["size"], "ms": round(L["ms"], 6)}
+                                            for L in r["launches"]],
+                               "accuracy_vs_fp64": sweep_errors(insts, r["fields"], ref, r["diags"], dref)}
+    del sw
+    if not args.only_headline:
+        if not args.no_full_model:
+            out["full_model_pulse"] = full_model_measurement(torch, args)
+        if not args.no_paper_shapes:
+            out["paper_shapes"] = paper_shapes_measurement(torch)
+        if not args.no_long_pulse:
+            out["long_pulse"] = long_pulse_measurement(torch, [int(x) for x in args.long_pulse_checkpoints.split(",")])
+        if not args.no_parareal:
+            out["parareal"] = parareal_measurement(torch, "fp32_cn64")
+            out["parareal_fp32_storage"] = parareal_measurement(torch, "fp32_storage")
+        if not args.no_net:
+            out["coarse_net"] = coarse_net_measurement(torch)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
+
+
+def wl_batch_steps():
+    from paper_1507_05988_amd import workloads as wl
+
+    return wl.BATCH_STEPS
 
 
 if __name__ == "__main__":

@@ -190,6 +190,16 @@ fcn_status fcn_plan_destroy(fcn_plan_t plan);
 fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, double *row_ms, double *col_ms,
                           double *total_ms);
 
+/* Per-launch kernel timing: like fcn_step_timed, and returns the mean duration [ms] of every
+ * kernel launch of the steady step body (events recorded by the kernels themselves).  A step is
+ * one row-pass launch per distinct nt of the plan (ascending nt), then one column-pass launch per
+ * distinct nr (ascending nr): *n_launches of them.  launch_ms[l] receives the mean duration of
+ * launch l; launch_info[3 l .. 3 l + 2] receive {pass: 0 row, 1 column; its nt or nr; the grid
+ * points the launch covers}.  max_launches: capacity of both host arrays (FCN_E_SIZE, with
+ * *n_launches set, when too small).  Synchronous; 2 <= nsteps <= 10000. */
+fcn_status fcn_step_timed_launches(fcn_plan_t plan, void *field_dev, int64_t nsteps, int32_t max_launches,
+                                   int32_t *n_launches, double *launch_ms, int64_t *launch_info);
+
 /* Allocation-free variant of fcn_step, for callers that cannot allocate device memory (code
  * that must not call hipMalloc, tight serving loops, harnesses that forbid allocation).
  * Instead of the caller-owned workspace of fcn_plan_bind it uses the library's own static

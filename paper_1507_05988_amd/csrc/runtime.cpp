@@ -442,8 +442,9 @@ struct StepCtx {
 
 // e0 / e1: optional events recorded at the start of the pass's first kernel and the end of
 // its last kernel.
+// lev: optional events, two per launch (start, end), recorded by each launch itself.
 hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, int seed, double stage_len = 0.0,
-                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const hipEvent_t *lev = nullptr) {
     const size_t nb = p->row_buckets.size();
     for (size_t bi = 0; bi < nb; bi++) {
         const auto &b = p->row_buckets[bi];
@@ -454,23 +455,26 @@ hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, in
         a.seed_slots = seed;
         a.stage_len = stage_len;
         const bool nl = (flags & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
-        hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)), nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
-                                  bi == 0 ? e0 : nullptr, bi + 1 == nb ? e1 : nullptr);
+        hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)),
+                                  nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
+                                  lev ? lev[2 * bi] : (bi == 0 ? e0 : nullptr),
+                                  lev ? lev[2 * bi + 1] : (bi + 1 == nb ? e1 : nullptr));
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0, hipEvent_t e0 = nullptr,
-                    hipEvent_t e1 = nullptr) {
+                    hipEvent_t e1 = nullptr, const hipEvent_t *lev = nullptr) {
     const size_t nb = p->col_buckets.size();
     for (size_t bi = 0; bi < nb; bi++) {
         const auto &b = p->col_buckets[bi];
         ColArgs a = col_args(p, field, b);
         a.use_stage_len = stage;
         a.stage_len = stage_len;
-        hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, p->stream, bi == 0 ? e0 : nullptr,
-                                  bi + 1 == nb ? e1 : nullptr);
+        hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, p->stream,
+                                  lev ? lev[2 * bi] : (bi == 0 ? e0 : nullptr),
+                                  lev ? lev[2 * bi + 1] : (bi + 1 == nb ? e1 : nullptr));
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -894,6 +898,69 @@ fcn_status fcn_step_timed(fcn_plan_t p, void *field_dev, int64_t nsteps, double 
     *col_ms = csum / (double)mid;
     *row_ms = rsum / (double)mid;
     *total_ms = tot;
+    return FCN_OK;
+}
+
+fcn_status fcn_step_timed_launches(fcn_plan_t p, void *field_dev, int64_t nsteps, int32_t max_launches,
+                                   int32_t *n_launches, double *launch_ms, int64_t *launch_info) {
+    if (!p) return FCN_E_ARG;
+    p->err.clear();
+    if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
+    if (!field_dev || !n_launches) return fail(p, FCN_E_ARG, "NULL argument");
+    if (nsteps < 2 || nsteps > 10000) return fail(p, FCN_E_ARG, "nsteps must be in [2, 10000]");
+    const int nrow = (int)p->row_buckets.size(), ncol = (int)p->col_buckets.size(), nl = nrow + ncol;
+    *n_launches = nl;
+    if (max_launches < nl || !launch_ms || !launch_info)
+        return fail(p, FCN_E_SIZE, "the plan's step has %d launches; buffers hold %d", nl, max_launches);
+    // per steady step: column launches then row launches, two events each
+    const int64_t mid = nsteps - 1;
+    std::vector<hipEvent_t> ev((size_t)(2 * nl * mid), nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    StepCtx ctx;
+    if (e == hipSuccess && p->opt.adaptive && !p->seeded) {
+        e = row_pass(p, field_dev, F_DIAG, ctx, 1);
+        p->seeded = true;
+    }
+    if (e == hipSuccess) e = row_pass(p, field_dev, F_FIRST, ctx, 0);
+    for (int64_t s = 0; s < mid && e == hipSuccess; s++) {
+        const hipEvent_t *base = ev.data() + (size_t)(2 * nl * s);
+        e = col_pass(p, field_dev, 0, 0.0, nullptr, nullptr, base + 2 * nrow);
+        if (e == hipSuccess) e = row_pass(p, field_dev, F_MIDDLE, ctx, 0, 0.0, nullptr, nullptr, base);
+    }
+    if (e == hipSuccess) e = col_pass(p, field_dev, 0);
+    if (e == hipSuccess) e = row_pass(p, field_dev, F_LAST, ctx, 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    std::vector<double> sum((size_t)nl, 0.0);
+    for (int64_t s = 0; s < mid && e == hipSuccess; s++)
+        for (int l = 0; l < nl && e == hipSuccess; l++) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[(size_t)(2 * nl * s + 2 * l)], ev[(size_t)(2 * nl * s + 2 * l + 1)]);
+            sum[l] += ms;
+        }
+    for (auto &x : ev)
+        if (x) hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(p, e, "timed launches");
+    p->n_host += nsteps;
+    for (int l = 0; l < nl; l++) {
+        launch_ms[l] = sum[l] / (double)mid;
+        int64_t pts = 0;
+        if (l < nrow) {
+            const auto &b = p->row_buckets[l];
+            for (const auto &d : p->dinst)
+                if (d.nt == b.nt) pts += (int64_t)d.nr * d.nt;
+            launch_info[3 * l] = 0;
+            launch_info[3 * l + 1] = b.nt;
+        } else {
+            const auto &b = p->col_buckets[l - nrow];
+            for (const auto &d : p->dinst)
+                if (d.nr == b.nr) pts += (int64_t)d.nr * d.nt;
+            launch_info[3 * l] = 1;
+            launch_info[3 * l + 1] = b.nr;
+        }
+        launch_info[3 * l + 2] = pts;
+    }
     return FCN_OK;
 }
 

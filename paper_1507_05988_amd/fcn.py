@@ -29,7 +29,7 @@ EXPORTED = (
     "fcn_net_create", "fcn_net_param_count", "fcn_net_workspace_size", "fcn_net_bind", "fcn_net_refresh",
     "fcn_net_input", "fcn_net_forward", "fcn_net_target", "fcn_net_loss", "fcn_net_backward", "fcn_net_adam",
     "fcn_net_apply", "fcn_net_last_error", "fcn_net_destroy", "fcn_parareal_update",
-    "fcn_parareal_workspace_size", "fcn_parareal", "fcn_step_scratch",
+    "fcn_parareal_workspace_size", "fcn_parareal", "fcn_step_scratch", "fcn_step_timed_launches",
 )
 SCRATCH_BYTES = 4 << 20  # FCN_SCRATCH_BYTES
 PARAREAL_MAX_ITER = 64
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
         "fcn_plan_bind": ([vp, vp, sz, vp], ctypes.c_int),
         "fcn_step": ([vp, vp, i64], ctypes.c_int),
         "fcn_step_scratch": ([vp, vp, i64, vp], ctypes.c_int),
+        "fcn_step_timed_launches": ([vp, vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl),
+                                     ctypes.POINTER(i64)], ctypes.c_int),
         "fcn_propagate": ([vp, vp, i64, vp, i32, vp, i32], ctypes.c_int),
         "fcn_diagnostics": ([vp, vp, vp], ctypes.c_int),
         "fcn_stage": ([vp, i32, vp, dbl], ctypes.c_int),
@@ -275,6 +277,18 @@ class Plan:
         self._check(self.lib.fcn_step_timed(self._h, self._field_ptr(field), int(nsteps), ctypes.byref(r),
                                             ctypes.byref(c), ctypes.byref(t)))
         return r.value, c.value, t.value
+
+    def step_timed_launches(self, field, nsteps: int):
+        """Steps with HIP events around every launch; returns a list of dicts
+        {pass: "row"|"col", size: nt or nr, points, ms} in launch order."""
+        cap = 64
+        n = ctypes.c_int32()
+        ms = (ctypes.c_double * cap)()
+        info = (ctypes.c_int64 * (3 * cap))()
+        self._check(self.lib.fcn_step_timed_launches(self._h, self._field_ptr(field), int(nsteps), cap,
+                                                     ctypes.byref(n), ms, info))
+        return [{"pass": "row" if info[3 * i] == 0 else "col", "size": int(info[3 * i + 1]),
+                 "points": int(info[3 * i + 2]), "ms": ms[i]} for i in range(n.value)]
 
     def stage(self, stage: int, field, length: float = 0.0):
         self._check(self.lib.fcn_stage(self._h, int(stage), self._field_ptr(field), float(length)))

@@ -177,7 +177,9 @@ def kernel_name(precision, launch, tiles):
         e = 16 if nt >= 4096 or (precision in ("fp64", "fp32_storage") and nt >= 2048) else 8
         r = "double" if precision in ("fp64", "fp32_storage") else "float"
         st = "double" if precision == "fp64" else "float"
-        flags = 63 + (256 if precision == "fp32_cn64" else 0)  # iFFT, NL, diagnostics, NL, FFT, store
+        # iFFT, NL, diagnostics, NL, FFT, store (63); twiddle pairs (256); the sweep is Kerr only:
+        # no density or absorption term, the phase-only nonlinear step (512)
+        flags = 63 + (256 if precision == "fp32_cn64" else 0) + 512
         return f"row_kernel<{r}, {st}, {nt}, {e}, {flags}>"
     r = "float" if precision == "fp32" else "double"
     st = "double" if precision == "fp64" else "float"

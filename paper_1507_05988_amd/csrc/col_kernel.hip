@@ -11,17 +11,24 @@
 // c_m and f_m use (1 + 1/2m): the centred 1/r dA/dr term adds +1/(2m dr^2) to the A_{m+1}
 // coefficient (Eqs. diff2-diff3); the printed (1 - 1/2m) would cancel it.
 //
-// Layout: the spectrum is [nr][nt] with p contiguous, so a workgroup takes W adjacent
-// frequencies (lanes read W consecutive complex values of a row: coalesced) and all nr rows.
+// Layout: the spectrum is [nr][nt] with p contiguous.  Frequencies p and nt - p have the same
+// matrices (only omega_p^2 enters), so a thread solves the pair together: the elimination
+// factors, pivots and reduced-system coefficients depend on the operator only and are
+// computed once for both right-hand sides.  A workgroup takes W adjacent pair slots
+// s = p0 .. p0+W-1 (columns s and nt - s; s = 0 and s = nt/2 are their own partners) and all nr
+// rows, so lanes read W consecutive complex values of a row in each of the two column groups.
 // The tridiagonal solve is a partitioned ("divide and conquer") elimination without
 // pivoting, so each element is read once and written once:
-//   1. thread (p, k) owns rows [kL, kL+L) of column p: it forms the right-hand side
+//   1. thread (s, k) owns rows [kL, kL+L) of its two columns: it forms the right-hand sides
 //      M_def x from its rows and one halo row on each side, then eliminates its interior
 //      rows 1..L-2 so every interior unknown is x_i = D_i - A_i x_first - C_i x_last;
-//   2. substituting that into its first and last rows gives two equations that couple only
-//      chunk boundary unknowns: a tridiagonal system of 2S unknowns per column (S chunks),
-//      solved in LDS by parallel cyclic reduction;
-//   3. each thread back-substitutes its interior rows and writes its L outputs.
+//   2. substituting that into its first and last rows gives two equations per chunk coupling
+//      only chunk-boundary unknowns (2S unknowns per column, S chunks); one cyclic-reduction
+//      step eliminates every chunk's last unknown using the neighbouring chunk's equation,
+//      leaving an S-unknown tridiagonal system in the chunks' first unknowns, solved in LDS by
+//      parallel cyclic reduction (log2 S levels, one equation per thread);
+//   3. each thread recovers its last unknown from its own equation and the next chunk's first
+//      unknown, back-substitutes its interior rows and writes its L outputs of both columns.
 // No pivoting is needed: with W = diag(1/8, 1, 2, ...) the operator dz/2 L is
 // W-skew-Hermitian, so after the diagonal similarity W^(1/2) the matrix I - dz/2 L has
 // Hermitian part I, which keeps every elimination (any symmetric ordering) well posed.
@@ -31,11 +38,6 @@
 #include "cplx.hpp"
 
 namespace fcn {
-
-template <typename R>
-struct Eq {  // lower, upper, rhs of one normalised (unit diagonal) reduced equation
-    c2<R> l, u, r;
-};
 
 // 1 / z for the pivots of the elimination.  They depend on the operator only, never on the
 // field, and |z|^2 stays of order one (the matrix has Hermitian part I after the diagonal
@@ -57,12 +59,17 @@ __device__ __forceinline__ c2<R> pivot_rcp(c2<R> z) {
     return mk<R>(z.x * r, -z.y * r);
 }
 
+// a - b c for complex values
+template <typename R>
+__device__ __forceinline__ c2<R> cmsub(c2<R> a, c2<R> b, c2<R> c) {
+    return mk<R>(fma(-b.x, c.x, fma(b.y, c.y, a.x)), fma(-b.x, c.y, fma(-b.y, c.x, a.y)));
+}
+
 // R: arithmetic precision; ST: storage precision of the spectrum (see the row kernel).
 template <typename R, typename ST, int W, int L>
 __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     static_assert(L >= 4, "at least two interior rows per chunk");
     extern __shared__ unsigned char smem_raw[];
-    Eq<R> *red = reinterpret_cast<Eq<R> *>(smem_raw);  // [W][2S + 1]
 
     // Workgroups are dispatched round-robin over the 8 XCDs (b -> XCD b mod 8).  Give each
     // XCD a contiguous range of column tiles so tiles sharing 128-byte lines (W*sizeof < 128)
@@ -77,11 +84,20 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const int pl = t % W;
     const int k = t / W;
     const int S = blockDim.x / W;
-    const int nred = 2 * S;
-    const int p = it.p0 + pl;
-    // one spare entry per column: a stride of 2S entries would put the W columns of a
-    // wavefront on the same LDS banks (2S * sizeof(Eq) is a multiple of 256 bytes)
-    Eq<R> *myred = red + pl * (nred + 1);
+    // reduced equations in LDS, one array per coefficient ([W][S + 1], one spare entry per
+    // column), so neighbouring chunks are neighbouring 8- or 16-byte words
+    const int S1 = S + 1;
+    c2<R> *q_l = reinterpret_cast<c2<R> *>(smem_raw);
+    c2<R> *q_u = q_l + W * S1;
+    c2<R> *q_r0 = q_u + W * S1;
+    c2<R> *q_r1 = q_r0 + W * S1;
+    const int me = pl * S1 + k;
+
+    const int slot = it.p0 + pl;          // columns slot and nt - slot
+    const bool live = slot <= nt / 2;     // the last tile of an instance can be partly empty
+    const int p1 = live ? slot : 0;
+    const int p2 = (nt - p1) & (nt - 1);  // p1 itself for slots 0 and nt/2
+    const bool store2 = live && p2 != p1;
 
     int64_t n = 0;
     double dz;
@@ -91,22 +107,25 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
         n = a.state->cnt_col;
         dz = a.dz_ring[(n & 1) * a.batch + it.inst];
     }
-    const int q = p < nt / 2 ? p : p - nt;
+    // q^2 = slot^2 for both columns (q = slot for p1 < nt/2, q = -nt/2 for p1 = nt/2)
     const R s = R(dz * in.diff_unit);
-    const R g = R((double)q * (double)q * in.gvd_unit * dz);
+    const R g = R((double)p1 * (double)p1 * in.gvd_unit * dz);
     const R bi_in = R(2) * s - g;      // Im b, interior rows
     const R bi_ax = R(4) * s - g;      // Im b, axis row
     const double *rc = a.rowcoef + 2 * (int64_t)in.rowcoef_off;
 
-    c2<ST> *col = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + p;
+    c2<ST> *col1 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + p1;
+    c2<ST> *col2 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + p2;
     const int m0 = k * L;
 
-    // ---- load rows m0-1 .. m0+L (halo included); rows outside [0, nr) read as 0
-    c2<R> x[L + 2];
+    // ---- load rows m0-1 .. m0+L (halo included) of both columns; rows outside [0, nr) read as 0
+    c2<ST> x1[L + 2], x2[L + 2];
 #pragma unroll
     for (int i = 0; i < L + 2; i++) {
         const int m = m0 - 1 + i;
-        x[i] = (m >= 0 && m < nr) ? ccast<R, ST>(col[(int64_t)m * nt]) : czero<R>();
+        const bool in_range = live && m >= 0 && m < nr;
+        x1[i] = in_range ? col1[(int64_t)m * nt] : mk<ST>(ST(0), ST(0));
+        x2[i] = in_range ? col2[(int64_t)m * nt] : mk<ST>(ST(0), ST(0));
     }
 
     // Row m of M_abc as (l, b, u) = (i lr, 1 + i bi, i ur) and of M_def x, computed on the fly.
@@ -128,121 +147,174 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
         }
     };
     // d x_{m-1} + e x_m + f x_{m+1} with d = -l, e = conj(b), f = -u (zero on the r_max row)
-    auto rhs_of = [&](int i, R lr, R bi, R ur) -> c2<R> {
+    auto rhs_of = [&](const c2<ST> (&x)[L + 2], int i, R lr, R bi, R ur) -> c2<R> {
         const int m = m0 + i;
         if (m >= nr - 1) return czero<R>();
-        const c2<R> xm = x[i + 1];
+        const c2<R> xm = ccast<R, ST>(x[i + 1]);
         c2<R> v = mk<R>(xm.x + bi * xm.y, xm.y - bi * xm.x);
-        v = cadd<R>(v, cmul_i<R>(x[i], -lr));
-        return cadd<R>(v, cmul_i<R>(x[i + 2], -ur));
+        v = cadd<R>(v, cmul_i<R>(ccast<R, ST>(x[i]), -lr));
+        return cadd<R>(v, cmul_i<R>(ccast<R, ST>(x[i + 2]), -ur));
     };
 
     R lr0, bi0, ur0, lrL, biL, urL;
     row_coef(0, lr0, bi0, ur0);
     row_coef(L - 1, lrL, biL, urL);
-    const c2<R> rhs0 = rhs_of(0, lr0, bi0, ur0);
-    const c2<R> rhsL = rhs_of(L - 1, lrL, biL, urL);
+    const c2<R> rhs0_1 = rhs_of(x1, 0, lr0, bi0, ur0), rhs0_2 = rhs_of(x2, 0, lr0, bi0, ur0);
+    const c2<R> rhsL_1 = rhs_of(x1, L - 1, lrL, biL, urL), rhsL_2 = rhs_of(x2, L - 1, lrL, biL, urL);
 
     // ---- local elimination of interior rows 1..L-2:  x_i = rp_i - sp_i x_first - mu_i x_{i+1}
-    c2<R> mu[L], rp[L], sp[L];
+    // (mu, sp: the operator's, shared by both columns; rp1, rp2: one per column)
+    c2<R> mu[L], sp[L], rp1[L], rp2[L];
     {
         R lr, bi, ur;
         row_coef(1, lr, bi, ur);
         c2<R> ip = pivot_rcp<R>(mk<R>(R(1), bi));
-        mu[1] = cmul<R>(mk<R>(R(0), ur), ip);
-        rp[1] = cmul<R>(rhs_of(1, lr, bi, ur), ip);
-        sp[1] = cmul<R>(mk<R>(R(0), lr), ip);
+        mu[1] = cmul_i<R>(ip, ur);
+        sp[1] = cmul_i<R>(ip, lr);
+        rp1[1] = cmul<R>(rhs_of(x1, 1, lr, bi, ur), ip);
+        rp2[1] = cmul<R>(rhs_of(x2, 1, lr, bi, ur), ip);
 #pragma unroll
         for (int i = 2; i <= L - 2; i++) {
             row_coef(i, lr, bi, ur);
             // pivot b_i - l_i mu_{i-1}
             const c2<R> lmu = cmul_i<R>(mu[i - 1], lr);
             ip = pivot_rcp<R>(mk<R>(R(1) - lmu.x, bi - lmu.y));
-            mu[i] = cmul<R>(mk<R>(R(0), ur), ip);
-            rp[i] = cmul<R>(csub<R>(rhs_of(i, lr, bi, ur), cmul_i<R>(rp[i - 1], lr)), ip);
+            mu[i] = cmul_i<R>(ip, ur);
             sp[i] = cmul<R>(cmul_i<R>(sp[i - 1], -lr), ip);
+            rp1[i] = cmul<R>(csub<R>(rhs_of(x1, i, lr, bi, ur), cmul_i<R>(rp1[i - 1], lr)), ip);
+            rp2[i] = cmul<R>(csub<R>(rhs_of(x2, i, lr, bi, ur), cmul_i<R>(rp2[i - 1], lr)), ip);
         }
     }
     // backward sweep for the representation of x_1 and x_{L-2} in (x_first, x_last)
-    c2<R> D = rp[L - 2], A = sp[L - 2], C = mu[L - 2];
-    const c2<R> Dl = D, Al = A, Cl = C;
+    c2<R> D1 = rp1[L - 2], D2 = rp2[L - 2], A = sp[L - 2], C = mu[L - 2];
+    const c2<R> Dl1 = D1, Dl2 = D2, Al = A, Cl = C;
 #pragma unroll
     for (int i = L - 3; i >= 1; i--) {
-        D = csub<R>(rp[i], cmul<R>(mu[i], D));
-        A = csub<R>(sp[i], cmul<R>(mu[i], A));
-        C = mk<R>(-(mu[i].x * C.x - mu[i].y * C.y), -(mu[i].x * C.y + mu[i].y * C.x));
+        D1 = cmsub<R>(rp1[i], mu[i], D1);
+        D2 = cmsub<R>(rp2[i], mu[i], D2);
+        A = cmsub<R>(sp[i], mu[i], A);
+        C = cmul<R>(mu[i], mk<R>(-C.x, -C.y));
     }
     // D, A, C now describe x_1; Dl, Al, Cl describe x_{L-2}.
 
-    // ---- reduced equations of the chunk's first and last rows
-    // first: l_0 X_prev + (b_0 - u_0 A_1) x_first - u_0 C_1 x_last = r_0 - u_0 D_1
-    // last:  -l_{L-1} A_{L-2} x_first + (b_{L-1} - l_{L-1} C_{L-2}) x_last + u_{L-1} X_next
+    // ---- reduced equations of the chunk's first and last rows (unit diagonal)
+    // first (X_2k):   l0 X_{2k-1} + X_2k + u0 X_{2k+1} = r0
+    //   from l_0 X_prev + (b_0 - u_0 A_1) x_first - u_0 C_1 x_last = r_0 - u_0 D_1
+    // last (X_2k+1):  l1 X_2k + X_{2k+1} + u1 X_{2k+2} = r1
+    //   from -l_{L-1} A_{L-2} x_first + (b_{L-1} - l_{L-1} C_{L-2}) x_last + u_{L-1} X_next
     //        = r_{L-1} - l_{L-1} D_{L-2}
-    Eq<R> e0, e1;
+    c2<R> l0, u0, r0_1, r0_2, l1, u1, r1_1, r1_2;
     {
-        const c2<R> u0 = mk<R>(R(0), ur0);
-        const c2<R> uA = cmul<R>(u0, A);
+        const c2<R> uA = cmul_i<R>(A, ur0);
         const c2<R> idg = pivot_rcp<R>(mk<R>(R(1) - uA.x, bi0 - uA.y));
-        e0.l = cmul<R>(mk<R>(R(0), lr0), idg);
-        const c2<R> uC = cmul<R>(u0, C);
-        e0.u = cmul<R>(mk<R>(-uC.x, -uC.y), idg);
-        e0.r = cmul<R>(csub<R>(rhs0, cmul<R>(u0, D)), idg);
+        l0 = cmul_i<R>(idg, lr0);
+        u0 = cmul<R>(cmul_i<R>(C, -ur0), idg);
+        r0_1 = cmul<R>(csub<R>(rhs0_1, cmul_i<R>(D1, ur0)), idg);
+        r0_2 = cmul<R>(csub<R>(rhs0_2, cmul_i<R>(D2, ur0)), idg);
 
-        const c2<R> lL = mk<R>(R(0), lrL);
-        const c2<R> lC = cmul<R>(lL, Cl);
+        const c2<R> lC = cmul_i<R>(Cl, lrL);
         const c2<R> idg1 = pivot_rcp<R>(mk<R>(R(1) - lC.x, biL - lC.y));
-        const c2<R> lA = cmul<R>(lL, Al);
-        e1.l = cmul<R>(mk<R>(-lA.x, -lA.y), idg1);
-        e1.u = cmul<R>(mk<R>(R(0), urL), idg1);
-        e1.r = cmul<R>(csub<R>(rhsL, cmul<R>(lL, Dl)), idg1);
+        l1 = cmul<R>(cmul_i<R>(Al, -lrL), idg1);
+        u1 = cmul_i<R>(idg1, urL);
+        r1_1 = cmul<R>(csub<R>(rhsL_1, cmul_i<R>(Dl1, lrL)), idg1);
+        r1_2 = cmul<R>(csub<R>(rhsL_2, cmul_i<R>(Dl2, lrL)), idg1);
     }
 
-    // ---- parallel cyclic reduction on the 2S reduced unknowns of each column
-    const int i0 = 2 * k, i1 = 2 * k + 1;
-    myred[i0] = e0;
-    myred[i1] = e1;
+    // ---- one cyclic-reduction step: eliminate X_{2k-1} (the previous chunk's last equation)
+    // and X_{2k+1} (this chunk's) from this chunk's first equation.  Chunk 0 has l0 = 0.
+    q_l[me] = l1;
+    q_u[me] = u1;
+    q_r0[me] = r1_1;
+    q_r1[me] = r1_2;
     __syncthreads();
-    for (int h = 1; h < nred; h <<= 1) {
-        Eq<R> ne[2];
-#pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int i = i0 + j;
-            const Eq<R> me = j == 0 ? e0 : e1;
-            Eq<R> lo, hi;
-            if (i - h >= 0) lo = myred[i - h]; else lo = Eq<R>{czero<R>(), czero<R>(), czero<R>()};
-            if (i + h < nred) hi = myred[i + h]; else hi = Eq<R>{czero<R>(), czero<R>(), czero<R>()};
-            // eq_i - l_i eq_{i-h} - u_i eq_{i+h}, then renormalise
-            const c2<R> dg = csub<R>(csub<R>(mk<R>(R(1), R(0)), cmul<R>(me.l, lo.u)), cmul<R>(me.u, hi.l));
-            const c2<R> idg = pivot_rcp<R>(dg);
-            const c2<R> nl = cmul<R>(cmul<R>(me.l, lo.l), idg);
-            const c2<R> nu = cmul<R>(cmul<R>(me.u, hi.u), idg);
-            const c2<R> nrh = cmul<R>(csub<R>(csub<R>(me.r, cmul<R>(me.l, lo.r)), cmul<R>(me.u, hi.r)), idg);
-            ne[j] = Eq<R>{mk<R>(-nl.x, -nl.y), mk<R>(-nu.x, -nu.y), nrh};
+    c2<R> pl1 = czero<R>(), pu1 = czero<R>(), pr1 = czero<R>(), pr2 = czero<R>();
+    if (k > 0) {
+        pl1 = q_l[me - 1];
+        pu1 = q_u[me - 1];
+        pr1 = q_r0[me - 1];
+        pr2 = q_r1[me - 1];
+    }
+    c2<R> yl, yu, yr1, yr2;  // Y_{k-1}, Y_{k+1} coefficients and right-hand sides, unit diagonal
+    {
+        const c2<R> dg = cmsub<R>(cmsub<R>(mk<R>(R(1), R(0)), l0, pu1), u0, l1);
+        const c2<R> idg = pivot_rcp<R>(dg);
+        const c2<R> nl = cmul<R>(cmul<R>(l0, pl1), idg);
+        const c2<R> nu = cmul<R>(cmul<R>(u0, u1), idg);
+        yl = mk<R>(-nl.x, -nl.y);
+        yu = mk<R>(-nu.x, -nu.y);
+        yr1 = cmul<R>(cmsub<R>(cmsub<R>(r0_1, l0, pr1), u0, r1_1), idg);
+        yr2 = cmul<R>(cmsub<R>(cmsub<R>(r0_2, l0, pr2), u0, r1_2), idg);
+    }
+    __syncthreads();
+
+    // ---- parallel cyclic reduction on the S equations Y_k of each column pair
+    q_l[me] = yl;
+    q_u[me] = yu;
+    q_r0[me] = yr1;
+    q_r1[me] = yr2;
+    __syncthreads();
+    for (int h = 1; h < S; h <<= 1) {
+        c2<R> ll = czero<R>(), lu = czero<R>(), lr1 = czero<R>(), lr2 = czero<R>();
+        c2<R> hl = czero<R>(), hu = czero<R>(), hr1 = czero<R>(), hr2 = czero<R>();
+        if (k - h >= 0) {
+            ll = q_l[me - h];
+            lu = q_u[me - h];
+            lr1 = q_r0[me - h];
+            lr2 = q_r1[me - h];
         }
+        if (k + h < S) {
+            hl = q_l[me + h];
+            hu = q_u[me + h];
+            hr1 = q_r0[me + h];
+            hr2 = q_r1[me + h];
+        }
+        // eq_k - l_k eq_{k-h} - u_k eq_{k+h}, then renormalise (operator part shared)
+        const c2<R> dg = cmsub<R>(cmsub<R>(mk<R>(R(1), R(0)), yl, lu), yu, hl);
+        const c2<R> idg = pivot_rcp<R>(dg);
+        const c2<R> nl = cmul<R>(cmul<R>(yl, ll), idg);
+        const c2<R> nu = cmul<R>(cmul<R>(yu, hu), idg);
+        yr1 = cmul<R>(cmsub<R>(cmsub<R>(yr1, yl, lr1), yu, hr1), idg);
+        yr2 = cmul<R>(cmsub<R>(cmsub<R>(yr2, yl, lr2), yu, hr2), idg);
+        yl = mk<R>(-nl.x, -nl.y);
+        yu = mk<R>(-nu.x, -nu.y);
         __syncthreads();
-        e0 = ne[0];
-        e1 = ne[1];
-        myred[i0] = e0;
-        myred[i1] = e1;
+        q_l[me] = yl;
+        q_u[me] = yu;
+        q_r0[me] = yr1;
+        q_r1[me] = yr2;
         __syncthreads();
     }
-    const c2<R> xf = e0.r;  // x_first
-    const c2<R> xl = e1.r;  // x_last
+    // x_first of both columns; x_last from this chunk's last equation and the next chunk's first
+    const c2<R> xf1 = yr1, xf2 = yr2;
+    c2<R> nf1 = czero<R>(), nf2 = czero<R>();
+    if (k + 1 < S) {
+        nf1 = q_r0[me + 1];
+        nf2 = q_r1[me + 1];
+    }
+    const c2<R> xl1 = cmsub<R>(cmsub<R>(r1_1, l1, xf1), u1, nf1);
+    const c2<R> xl2 = cmsub<R>(cmsub<R>(r1_2, l1, xf2), u1, nf2);
 
     // ---- back-substitution and store
-    c2<R> out[L];
-    out[0] = xf;
-    out[L - 1] = xl;
-    c2<R> nxt = xl;
+    c2<R> o1[L], o2[L];
+    o1[0] = xf1;
+    o2[0] = xf2;
+    o1[L - 1] = xl1;
+    o2[L - 1] = xl2;
+    c2<R> n1 = xl1, n2 = xl2;
 #pragma unroll
     for (int i = L - 2; i >= 1; i--) {
-        nxt = csub<R>(csub<R>(rp[i], cmul<R>(sp[i], xf)), cmul<R>(mu[i], nxt));
-        out[i] = nxt;
+        n1 = cmsub<R>(cmsub<R>(rp1[i], sp[i], xf1), mu[i], n1);
+        n2 = cmsub<R>(cmsub<R>(rp2[i], sp[i], xf2), mu[i], n2);
+        o1[i] = n1;
+        o2[i] = n2;
     }
 #pragma unroll
     for (int i = 0; i < L; i++) {
         const int m = m0 + i;
-        if (m < nr) col[(int64_t)m * nt] = ccast<ST, R>(out[i]);
+        if (live && m < nr) {
+            col1[(int64_t)m * nt] = ccast<ST, R>(o1[i]);
+            if (store2) col2[(int64_t)m * nt] = ccast<ST, R>(o2[i]);
+        }
     }
 
     if (!a.use_stage_len && t == 0) {
@@ -259,7 +331,7 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
     const int S = (nr + L - 1) / L;
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
-    const size_t shm = sizeof(Eq<R>) * (size_t)W * (2 * S + 1);
+    const size_t shm = 4 * sizeof(c2<R>) * (size_t)W * (S + 1);
     hipExtLaunchKernelGGL((col_kernel<R, ST, W, L>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1, 0, a);
     return hipGetLastError();
 }

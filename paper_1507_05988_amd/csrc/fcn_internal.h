@@ -62,7 +62,8 @@ struct RowItem {
     int32_t m;
 };
 
-// Work item of the column pass: W frequencies [p0, p0+W) of one instance.
+// Work item of the column pass: W pair slots [p0, p0+W) of one instance, slot s standing for
+// the frequency columns s and nt - s (slots beyond nt/2 are empty).
 struct ColItem {
     int32_t inst;
     int32_t p0;
@@ -80,6 +81,8 @@ enum : int {
     RK_SCAN = 128,      // some instance of the launch has a density term: contiguous-chunk
                         // layout and the density scan (otherwise pointwise, strided layout)
     RK_TW_PAIR = 256,   // FP32 transforms with twiddles carried as hi + lo pairs
+    RK_NOABS = 512,     // no instance of the launch has a density or absorption term (MPA,
+                        // collisions): the nonlinear step is the Kerr phase rotation alone
 };
 
 // Step-length source of a row kernel.

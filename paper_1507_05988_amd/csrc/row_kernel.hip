@@ -44,12 +44,6 @@ __device__ __forceinline__ double ipow(double x, int k) {
     return r;
 }
 
-// A exp(decay + i phase) written as A + A delta with
-//   delta = expm1(decay) (cos phase + i sin phase) + (cos phase - 1) + i sin phase,
-//   cos phase - 1 = -2 sin^2(phase/2),  sin phase = 2 sin(phase/2) cos(phase/2),
-// so every small quantity keeps full relative precision.  Rounding exp(decay) and
-// cos(phase) themselves next to 1 would bias |A| by up to half an ulp per update, the
-// same way at every step (a systematic energy drift in FP32).
 __device__ __forceinline__ float ipowf_(float x, int k) {
     float r = 1.0f;
 #pragma unroll
@@ -60,21 +54,28 @@ __device__ __forceinline__ float ipowf_(float x, int k) {
     return r;
 }
 
-template <typename R>
-__device__ __forceinline__ c2<R> nl_rotate(c2<R> a, double decay, double phase);
-// sin and cos of |x| <= 0.4 by their Taylor series through x^9 and x^10 (truncation below
-// 1e-12 relative), expm1 of |x| <= 0.1 through x^7 (below 3e-12); other arguments take
-// the library functions.  Nonlinear phases per half step are usually in this range.
-__device__ __forceinline__ void sincos_small(float x, float *s, float *c) {
-    if (fabsf(x) <= 0.4f) {
-        const float x2 = x * x;
-        *s = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f + x2 * (-1.0f / 5040.0f + x2 * (1.0f / 362880.0f)))));
-        *c = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f + x2 * (-1.0f / 720.0f + x2 * (1.0f / 40320.0f +
-                                                                                  x2 * (-1.0f / 3628800.0f)))));
+// A exp(decay + i phase) written as A + A delta with
+//   delta = expm1(decay) (cos phase + i sin phase) + (cos phase - 1) + i sin phase,
+// with cos phase - 1 and expm1(decay) evaluated directly, so every small quantity keeps full
+// relative precision.  Rounding exp(decay) and cos(phase) themselves next to 1 would bias |A|
+// by up to half an ulp per update, the same way at every step (a systematic energy drift in
+// FP32).
+// sin(th) and cos(th) - 1 in FP32: Taylor series through th^9 and th^10 for |th| <= 0.4
+// (truncation below 1.1e-12 of the value), the library functions beyond.  cos(th) - 1 comes
+// from its own series, never from a rounded cos(th) next to 1.
+__device__ __forceinline__ void sin_cosm1(float th, float *sn, float *cm1) {
+    if (fabsf(th) <= 0.4f) {
+        const float t2 = th * th;
+        *sn = th * (1.0f + t2 * (-1.0f / 6.0f + t2 * (1.0f / 120.0f + t2 * (-1.0f / 5040.0f + t2 * (1.0f / 362880.0f)))));
+        *cm1 = t2 * (-0.5f + t2 * (1.0f / 24.0f + t2 * (-1.0f / 720.0f + t2 * (1.0f / 40320.0f +
+                                                                            t2 * (-1.0f / 3628800.0f)))));
     } else {
-        sincosf(x, s, c);
+        float c;
+        sincosf(th, sn, &c);
+        *cm1 = c - 1.0f;
     }
 }
+// expm1 of |x| <= 0.1 through x^7 (truncation below 3e-12), the library function beyond.
 __device__ __forceinline__ float expm1_small(float x) {
     if (fabsf(x) <= 0.1f)
         return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f +
@@ -83,29 +84,30 @@ __device__ __forceinline__ float expm1_small(float x) {
     return expm1f(x);
 }
 
+// A exp(decay + i phase) = A + A delta, delta = e (cos + i sin) + (cos - 1) + i sin, e = expm1(decay)
 __device__ __forceinline__ c2<float> nl_rotate_f(c2<float> a, float decay, float phase) {
     const float em1 = expm1_small(decay);
-    float sh, ch;
-    sincos_small(0.5f * phase, &sh, &ch);
-    const float sn = 2.0f * sh * ch;
-    const float c1 = -2.0f * sh * sh;
+    float sn, c1;
+    sin_cosm1(phase, &sn, &c1);
     const float dr = em1 * (1.0f + c1) + c1;
     const float di = sn * (1.0f + em1);
     return mk<float>(a.x + (a.x * dr - a.y * di), a.y + (a.x * di + a.y * dr));
 }
-template <>
-__device__ __forceinline__ c2<float> nl_rotate<float>(c2<float> a, double decay, double phase) {
-    const float em1 = expm1f((float)decay);
-    float sh, ch;
-    sincosf(0.5f * (float)phase, &sh, &ch);
-    const float sn = 2.0f * sh * ch;
-    const float c1 = -2.0f * sh * sh;
-    const float dr = em1 * (1.0f + c1) + c1;
-    const float di = sn * (1.0f + em1);
-    return mk<float>(a.x + (a.x * dr - a.y * di), a.y + (a.x * di + a.y * dr));
+// A exp(i phase) = A + A ((cos - 1) + i sin): the pure phase rotation (no absorption term)
+__device__ __forceinline__ c2<float> nl_phase_f(c2<float> a, float phase) {
+    float sn, c1;
+    sin_cosm1(phase, &sn, &c1);
+    return mk<float>(a.x + (a.x * c1 - a.y * sn), a.y + (a.x * sn + a.y * c1));
 }
-template <>
-__device__ __forceinline__ c2<double> nl_rotate<double>(c2<double> a, double decay, double phase) {
+// FP64: cos phase - 1 = -2 sin^2(phase/2), sin phase = 2 sin(phase/2) cos(phase/2)
+__device__ __forceinline__ c2<double> nl_phase_d(c2<double> a, double phase) {
+    double sh, ch;
+    sincos(0.5 * phase, &sh, &ch);
+    const double sn = 2.0 * sh * ch;
+    const double c1 = -2.0 * sh * sh;
+    return mk<double>(a.x + (a.x * c1 - a.y * sn), a.y + (a.x * sn + a.y * c1));
+}
+__device__ __forceinline__ c2<double> nl_rotate_d(c2<double> a, double decay, double phase) {
     const double em1 = expm1(decay);
     double sh, ch;
     sincos(0.5 * phase, &sh, &ch);
@@ -306,7 +308,11 @@ struct NlPoint<double> {
     __device__ __forceinline__ c2<double> apply(c2<double> a, const DevInst &in, double h, double rho) const {
         const double im_n = kerr(in) + in.c_plasma * rho;
         const double re_n = in.c_mpa * ik1 + in.c_coll * rho;
-        return nl_rotate<double>(a, h * re_n, h * im_n);
+        return nl_rotate_d(a, h * re_n, h * im_n);
+    }
+    // N = i Kerr rate only (no absorption or density term in the launch)
+    __device__ __forceinline__ c2<double> apply_phase(c2<double> a, const DevInst &in, double h) const {
+        return nl_phase_d(a, h * kerr(in));
     }
 };
 
@@ -322,12 +328,13 @@ struct NlPoint<float> {
     __device__ __forceinline__ float dt_g(const DevInst &) const { return uk1 * u; }
     static __device__ __forceinline__ float dt_g_of(float umid, const DevInst &in) { return ipowf_(umid, in.K); }
     __device__ __forceinline__ float mid_arg(const NlPoint &o) const { return 0.5f * (u + o.u); }
-    __device__ __forceinline__ double kerr(const DevInst &in) const {
-        return (double)(u * (in.fk1 + u * (in.fk2 + u * (in.fk3 + u * in.fk4))));
+    __device__ __forceinline__ float kerr_f(const DevInst &in) const {
+        return u * (in.fk1 + u * (in.fk2 + u * (in.fk3 + u * in.fk4)));
     }
+    __device__ __forceinline__ double kerr(const DevInst &in) const { return (double)kerr_f(in); }
     __device__ __forceinline__ c2<float> apply(c2<float> a, const DevInst &in, float h, double rho,
                                                bool with_rho) const {
-        const float kr = u * (in.fk1 + u * (in.fk2 + u * (in.fk3 + u * in.fk4)));
+        const float kr = kerr_f(in);
         if (!with_rho) return nl_rotate_f(a, h * (in.f_mpa * uk1), h * kr);
         const double im_n = (double)kr + in.c_plasma * rho;
         const double re_n = (double)(in.f_mpa * uk1) + in.c_coll * rho;
@@ -335,6 +342,9 @@ struct NlPoint<float> {
     }
     __device__ __forceinline__ c2<float> apply(c2<float> a, const DevInst &in, float h, double rho) const {
         return apply(a, in, h, rho, true);
+    }
+    __device__ __forceinline__ c2<float> apply_phase(c2<float> a, const DevInst &in, float h) const {
+        return nl_phase_f(a, h * kerr_f(in));
     }
 };
 
@@ -348,13 +358,16 @@ struct NlPoint<float> {
 // The exact density step has S = 1 - exp(-int g dt) in [0, 1); an RK4 factor S outside [0, 1]
 // (a non-negative rate with sigma_K I^K dtau beyond the method's stability limit, 2.785 at
 // constant rate) sets *unstable: the density then leaves [0, rho_at] and runs away.
+// NOABS (launches whose instances have neither a density nor an absorption term, scan false):
+// N = i Kerr rate, a pure phase rotation.
 // Must be called by every thread of the workgroup (the scan holds barriers when T > 64).
-template <typename R, int T, int E>
+template <typename R, int T, int E, bool NOABS>
 __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevInst &in, R h, bool apply,
                                             bool diag, bool scan, bool upd_next, DiagAcc &acc, int tr,
                                             RowScratch &sh, int32_t *unstable) {
     using S_t = decltype(NlPoint<R>{}.dt_g(in));
-    const bool k1 = in.need_ik1 != 0.0;
+    constexpr bool F32 = std::is_same<R, float>::value;
+    const bool k1 = !NOABS && in.need_ik1 != 0.0;
     NlPoint<R> pt[E];
 #pragma unroll
     for (int k = 0; k < E; k++) pt[k].load(c[k], in, k1);
@@ -403,21 +416,37 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevI
         for (int k = 0; k < E; k++) rho[k] = 0.0;
     }
 
+    // FP32 kernels without the density keep the two maxima in FP32 (a maximum is exact in any
+    // precision) and convert once; the sum of intensities is always accumulated in FP64
+    float imax32 = 0.0f, phi32 = 0.0f;
 #pragma unroll
     for (int k = 0; k < E; k++) {
         if (diag) {
             const double I = pt[k].intensity();
             acc.sum += I;
-            acc.imax = fmax(acc.imax, I);
-            acc.rmax = fmax(acc.rmax, rho[k]);
-            acc.phimax = fmax(acc.phimax, in.phi_kerr * fabs(pt[k].kerr(in)) + in.phi_plasma * rho[k]);
+            if (F32 && !scan) {
+                if constexpr (F32) {
+                    imax32 = fmaxf(imax32, pt[k].ii);
+                    phi32 = fmaxf(phi32, fabsf(pt[k].kerr_f(in)));
+                }
+            } else {
+                acc.imax = fmax(acc.imax, I);
+                acc.rmax = fmax(acc.rmax, rho[k]);
+                acc.phimax = fmax(acc.phimax, in.phi_kerr * fabs(pt[k].kerr(in)) + in.phi_plasma * rho[k]);
+            }
         }
         if (apply) {
-            if constexpr (std::is_same<R, float>::value)
+            if constexpr (NOABS)
+                c[k] = pt[k].apply_phase(c[k], in, h);
+            else if constexpr (F32)
                 c[k] = pt[k].apply(c[k], in, h, rho[k], scan);
             else
                 c[k] = pt[k].apply(c[k], in, h, rho[k]);
         }
+    }
+    if (diag && F32 && !scan) {
+        acc.imax = fmax(acc.imax, (double)imax32);
+        acc.phimax = fmax(acc.phimax, in.phi_kerr * (double)phi32);
     }
     // the neighbour's first point with the density its own thread uses (the scan's prefix, not
     // this thread's replayed value, which may differ in the last bit): a fused pass then
@@ -520,6 +549,8 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
         // the density scan needs contiguous points per thread; a launch without any density
         // term applies the nonlinear step pointwise on the strided registers instead
         constexpr bool scan = (FLAGS & RK_SCAN) != 0;
+        constexpr bool NOABS = (FLAGS & RK_NOABS) != 0;
+        static_assert(!(scan && NOABS), "a launch without absorption or density has no scan");
         const R ha = R(0.5 * dz_a), hb = R(0.5 * dz_b);
         constexpr bool DO_A = (FLAGS & RK_NL_A) != 0;
         constexpr bool DO_B = (FLAGS & RK_NL_B) != 0;
@@ -534,9 +565,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
             for (int k = 0; k < E; k++) c[k] = row_lds[lpad(tr * E + k)];
             c2<R> nx = row_lds[lpad(tr < T - 1 ? tr * E + E : 0)];
             int32_t *unst = &a.state->unstable;
-            if constexpr (DO_A) nl_sub_step<R, T, E>(c, nx, in, ha, true, false, true, true, acc, tr, sh, unst);
+            if constexpr (DO_A) nl_sub_step<R, T, E, false>(c, nx, in, ha, true, false, true, true, acc, tr, sh, unst);
             if constexpr (DO_B || DO_D)
-                nl_sub_step<R, T, E>(c, nx, in, hb, DO_B, DO_D, true, false, acc, tr, sh, unst);
+                nl_sub_step<R, T, E, false>(c, nx, in, hb, DO_B, DO_D, true, false, acc, tr, sh, unst);
             if constexpr ((FLAGS & RK_STORE) != 0) {
                 __syncthreads();
 #pragma unroll
@@ -548,9 +579,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
         } else {
             c2<R> unused = czero<R>();
             int32_t *unst = &a.state->unstable;
-            if constexpr (DO_A) nl_sub_step<R, T, E>(v, unused, in, ha, true, false, false, false, acc, tr, sh, unst);
+            if constexpr (DO_A) nl_sub_step<R, T, E, NOABS>(v, unused, in, ha, true, false, false, false, acc, tr, sh, unst);
             if constexpr (DO_B || DO_D)
-                nl_sub_step<R, T, E>(v, unused, in, hb, DO_B, DO_D, false, false, acc, tr, sh, unst);
+                nl_sub_step<R, T, E, NOABS>(v, unused, in, hb, DO_B, DO_D, false, false, acc, tr, sh, unst);
         }
         if constexpr (DO_D) {
             acc = row_reduce<T>(acc, tr, sh);
@@ -645,6 +676,12 @@ static hipError_t launch_row_p(int nt, int flags, const RowArgs &a, int grid, hi
         case RK_LAST | RK_SCAN: return launch_row_nt<R, ST, (RK_LAST | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
         case RK_DIAG_ONLY | RK_SCAN: return launch_row_nt<R, ST, (RK_DIAG_ONLY | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
         case RK_T_NL | RK_SCAN: return launch_row_nt<R, ST, (RK_T_NL | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
+        case RK_FIRST | RK_NOABS: return launch_row_nt<R, ST, (RK_FIRST | RK_NOABS) | X>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE | RK_NOABS: return launch_row_nt<R, ST, (RK_MIDDLE | RK_NOABS) | X>(nt, a, grid, s, e0, e1);
+        case RK_LAST | RK_NOABS: return launch_row_nt<R, ST, (RK_LAST | RK_NOABS) | X>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY | RK_NOABS:
+            return launch_row_nt<R, ST, (RK_DIAG_ONLY | RK_NOABS) | X>(nt, a, grid, s, e0, e1);
+        case RK_T_NL | RK_NOABS: return launch_row_nt<R, ST, (RK_T_NL | RK_NOABS) | X>(nt, a, grid, s, e0, e1);
         case RK_T_FFT: return launch_row_nt<R, ST, (RK_T_FFT) | X>(nt, a, grid, s, e0, e1);
         case RK_T_IFFT: return launch_row_nt<R, ST, (RK_T_IFFT) | X>(nt, a, grid, s, e0, e1);
         default: return hipErrorInvalidValue;

@@ -41,7 +41,8 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct RowBucket {
     int nt;
-    int scan;  // RK_SCAN when an instance of the bucket has a density term
+    int scan;  // RK_SCAN when an instance of the bucket has a density term, RK_NOABS when none
+               // has a density or absorption term, else 0
     int item_off, nitems;
     int grid;
 };
@@ -340,9 +341,14 @@ fcn_status build_plan(fcn_plan_t p) {
         for (int i : kv.second)
             for (int m = 0; m < p->insts[i].nr; m++) p->row_items.push_back(RowItem{i, m});
         b.nitems = (int)p->row_items.size() - b.item_off;
-        b.scan = 0;
-        for (int i : kv.second)
+        // the density scan if any instance has a density term; otherwise the phase-only step
+        // if no instance has an absorption term either
+        b.scan = RK_NOABS;
+        for (int i : kv.second) {
             if (p->dinst[i].need_rho != 0.0) b.scan = RK_SCAN;
+            if (p->dinst[i].c_mpa != 0.0 || p->dinst[i].c_coll != 0.0)
+                if (b.scan != RK_SCAN) b.scan = 0;
+        }
         const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)));
         b.grid = (b.nitems + rpw - 1) / rpw;
         p->row_buckets.push_back(b);
@@ -357,8 +363,9 @@ fcn_status build_plan(fcn_plan_t p) {
         if (b.w * ((b.nr + b.l - 1) / b.l) > 512) return fail(p, FCN_E_SIZE, "nr=%d too large for the column solve", b.nr);
         if (!col_tiles_supported(b.w, b.l)) return fail(p, FCN_E_ARG, "column tile %dx%d not built", b.w, b.l);
         b.item_off = (int)p->col_items.size();
+        // pair slots s = 0 .. nt/2 (columns s and nt - s share their matrices), W per workgroup
         for (int i : kv.second)
-            for (int p0 = 0; p0 < p->insts[i].nt; p0 += b.w) p->col_items.push_back(ColItem{i, p0});
+            for (int s0 = 0; s0 <= p->insts[i].nt / 2; s0 += b.w) p->col_items.push_back(ColItem{i, s0});
         b.nitems = (int)p->col_items.size() - b.item_off;
         p->col_buckets.push_back(b);
         p->col_w = b.w;

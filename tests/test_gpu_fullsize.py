@@ -4,8 +4,12 @@ Each workload runs at its real grid (and batch) with the plan options bench.py u
 oracle follows the same steps on the whole field where that takes seconds, else on sampled
 instances of a batch (each instance of a batch is bit-identical to the instance run alone,
 tested separately, so a sampled instance checks the batched launch).  Tolerances: FP64 1e-10;
-FP32 and FP32-CN64 the per-step bound 1e-6 accumulated over the steps; FP32 storage 1e-6 over
-<= 100 steps.
+the FP32-field modes the FP32 target 1e-5 (FP32 storage 1e-6) in the r-weighted field norm, the
+relative error the target is stated in.  Element by element (largest element error over the
+largest element) the bound is ELEMENTWISE times that: the largest element error sits on the axis
+at the focus, where the r-weighted norm gives least weight, and measures 4-9 times the field
+error in every FP32 mode.  Plain FP32, which misses the target on the sweep's largest pulses, is
+held to the per-step bound 1e-6 accumulated over the steps under a test name that says so.
 """
 import math
 import sys
@@ -33,6 +37,13 @@ def werr(a, ref):
     return math.sqrt(np.sum(w[:, None] * np.abs(a - ref) ** 2) / np.sum(w[:, None] * np.abs(ref) ** 2))
 
 
+ELEMENTWISE = 10  # element-wise bound over the field-norm bound (see the module docstring)
+
+
+def elerr(a, ref):
+    return float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+
+
 def _run(insts, precision, nsteps, fields, **kw):
     plan = fcn.Plan(insts, precision=precision, **kw)
     f = plan.pack(fields)
@@ -41,36 +52,65 @@ def _run(insts, precision, nsteps, fields, **kw):
     return plan.unpack(f)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 60 * 1e-6), ("fp32_storage", 1e-6),
-                                           ("fp32_cn64", 60 * 1e-6)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("fp32_storage", 1e-6),
+                                           ("fp32_cn64", 1e-5)])
 def test_full_model_pulse_full_size(precision, tol):
-    """Full-model pulse, 512 x 2048, 60 steps of 5 mm from z = 0 (the bench workload)."""
+    """Full-model pulse, 512 x 2048, 60 steps of 5 mm from z = 0 (the bench workload), field
+    norm and element by element against the oracle from the same input."""
     inst = wl.config_full()
     a0 = wl.gaussian_field(inst)
     a_in = a0 if precision == "fp64" else a0.astype(np.complex64)
     got = _run(inst, precision, 60, a_in)[0].astype(np.complex128)
     want = oracle.propagate(inst, a_in.astype(np.complex128), 60)
-    e = werr(got, want)
-    say(f"  full model 512x2048, 60 steps, {precision}: {e:.3e}")
-    assert e < tol
+    e, el = werr(got, want), elerr(got, want)
+    say(f"  full model 512x2048, 60 steps, {precision}: field {e:.3e}, element-wise {el:.3e}")
+    assert e < tol and el < ELEMENTWISE * tol
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", wl.BATCH_STEPS * 1e-6), ("fp32_cn64", 1e-5)])
-def test_batched_sweep_full_size_sampled(precision, tol):
-    """The 64-pulse sweep (7.3e7 points) in one plan, 100 steps; the oracle runs the smallest,
-    a middle and the largest instance alone.  FP32: the per-step bound; FP32-CN64: the 1e-5
-    target over the whole run."""
+def _sweep_sampled(precision):
+    """The 64-pulse sweep (7.56e7 points) in one graph-replayed plan on its own stream, 100
+    steps; the oracle runs the smallest, a middle and the largest instance alone."""
+    import torch
     insts = wl.config_batch()
     fields = [wl.gaussian_field(i, np.complex64) for i in insts]
-    got = _run(insts, precision, wl.BATCH_STEPS, fields)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        got = _run(insts, precision, wl.BATCH_STEPS, fields, use_graph=True, stream=stream)
     sizes = [i["nr"] * i["nt"] for i in insts]
     order = np.argsort(sizes, kind="stable")
+    out = []
     for k in (order[0], order[len(order) // 2], order[-1]):
         inst = insts[k]
         want = oracle.propagate(inst, fields[k].astype(np.complex128), wl.BATCH_STEPS)
-        e = werr(got[k].astype(np.complex128), want)
-        say(f"  {precision} instance {k} ({inst['nr']}x{inst['nt']}): {e:.3e}")
-        assert e < tol
+        g = got[k].astype(np.complex128)
+        out.append((k, werr(g, want), elerr(g, want)))
+        say(f"  {precision} instance {k} ({inst['nr']}x{inst['nt']}): field {out[-1][1]:.3e}, "
+            f"element-wise {out[-1][2]:.3e}")
+    return insts, fields, got, out
+
+
+def test_batched_sweep_full_size_fp32_cn64():
+    """The headline mode on the headline workload: the sampled instances within the FP32 target
+    1e-5 of the oracle (field norm; element-wise within ELEMENTWISE times that), and every one of
+    the 64 instances within 1e-5 of the FP64 GPU method (which the oracle pins to 1e-10)."""
+    insts, fields, got, out = _sweep_sampled("fp32_cn64")
+    for k, e, el in out:
+        assert e < 1e-5 and el < ELEMENTWISE * 1e-5, (k, e, el)
+    ref = _run(insts, "fp64", wl.BATCH_STEPS, [f.astype(np.complex128) for f in fields])
+    k0 = out[0][0]
+    assert werr(ref[k0], oracle.propagate(insts[k0], fields[k0].astype(np.complex128), wl.BATCH_STEPS)) < 1e-10
+    errs = [werr(g.astype(np.complex128), r) for g, r in zip(got, ref)]
+    say(f"  all 64 instances vs FP64: max {max(errs):.3e}, median {np.median(errs):.3e}")
+    assert max(errs) < 1e-5
+
+
+def test_batched_sweep_full_size_plain_fp32_reported_not_at_target():
+    """Plain FP32 on the sweep is not at the 1e-5 target on its largest pulses (the FP32
+    elimination factors and twiddles repeat the same rounding every step); it is held to the
+    per-step bound 1e-6 accumulated over the 100 steps."""
+    _, _, _, out = _sweep_sampled("fp32")
+    for k, e, el in out:
+        assert e < wl.BATCH_STEPS * 1e-6 and el < ELEMENTWISE * wl.BATCH_STEPS * 1e-6, (k, e, el)
 
 
 def test_long_pulse_full_size_adaptive():
@@ -93,13 +133,15 @@ def test_long_pulse_full_size_adaptive():
     say(f"  long pulse 1024x8192 FP64 adaptive, {n} steps: {e:.3e}; dz {glog[0]:.3e} .. {glog[-1]:.3e}")
     assert np.max(np.abs(glog / wlog - 1)) < 1e-12
     assert e < 1e-10
-    p32 = fcn.Plan(inst, precision="fp32")
-    g = p32.pack(a0.astype(np.complex64))
-    p32.propagate(g, n, dz_log=log, replay=True)
-    p32.sync()
-    e32 = werr(p32.unpack(g)[0].astype(np.complex128), want)
-    say(f"  FP32 replay: {e32:.3e}")
-    assert e32 < n * 1e-6
+    for prec, tol in (("fp32", n * 1e-6), ("fp32_cn64", 1e-5)):
+        p32 = fcn.Plan(inst, precision=prec)
+        g = p32.pack(a0.astype(np.complex64))
+        p32.propagate(g, n, dz_log=log, replay=True)
+        p32.sync()
+        x = p32.unpack(g)[0].astype(np.complex128)
+        e32, el32 = werr(x, want), elerr(x, want)
+        say(f"  {prec} replay: field {e32:.3e}, element-wise {el32:.3e}")
+        assert e32 < tol and el32 < ELEMENTWISE * tol
 
 
 def test_learned_coarse_trajectory_full_size():
@@ -111,3 +153,24 @@ def test_learned_coarse_trajectory_full_size():
     e32 = werr(_run(inst, "fp32", 50, a0.astype(np.complex64))[0].astype(np.complex128), want)
     say(f"  trajectory 2000, 50 steps: FP64 {e64:.3e}, FP32 {e32:.3e}")
     assert e64 < 1e-10 and e32 < 50 * 1e-6
+
+
+@pytest.mark.parametrize("name", ["application_1350x1024", "timing_2112x2048"])
+def test_paper_grids_full_size(name):
+    """The paper's own grids at full size: the 1.1 km application run's Nr = 1350, Nt = 1024
+    (Sec. 5.2) and the timing example's Nr = 2112, Nt = 2048 (Sec. 5.1, Table 2), a few full-model
+    steps against the oracle on the whole field: FP64 within 1e-10, FP32-CN64 within the 1e-5
+    target (field norm and element-wise)."""
+    inst = wl.config_paper_application() if name.startswith("application") else wl.config_paper_timing()
+    a0 = wl.gaussian_field(inst)
+    n = 4
+    want = oracle.propagate(inst, a0, n)
+    got64 = _run(inst, "fp64", n, a0)[0]
+    e64 = werr(got64, want)
+    a32 = a0.astype(np.complex64)
+    want32 = oracle.propagate(inst, a32.astype(np.complex128), n)
+    got32 = _run(inst, "fp32_cn64", n, a32)[0].astype(np.complex128)
+    e32, el32 = werr(got32, want32), elerr(got32, want32)
+    say(f"  {name}, {n} steps: FP64 {e64:.3e}; FP32-CN64 field {e32:.3e}, element-wise {el32:.3e}")
+    assert e64 < 1e-10 and elerr(got64, want) < 1e-10
+    assert e32 < 1e-5 and el32 < 1e-5

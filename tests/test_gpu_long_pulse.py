@@ -108,9 +108,9 @@ def test_fp64_against_oracle_checkpoints(runs):
 
 def test_fp32_modes_against_fp64_checkpoints(runs):
     """The FP32-field modes replay the FP64 run's dz log.  Before the collapse: FP32 within the
-    per-step bound 1e-6 accumulated over the steps, FP32-CN64 within that bound and a third of
-    the FP32 error (the column solve sets most of the FP32 error on this wide beam), FP32
-    storage within 1e-5.  After it, FP32 storage within three times the floor (the FP64 run
+    per-step bound 1e-6 accumulated over the steps, FP32-CN64 within the 1e-5 target and a third
+    of the FP32 error (the column solve sets most of the FP32 error on this wide beam), FP32
+    storage within 1e-5.  After it, each mode within a stated multiple of the floor (the FP64 run
     from the same FP32-rounded input)."""
     _, out = runs
     for n, r in out.items():
@@ -119,8 +119,13 @@ def test_fp32_modes_against_fp64_checkpoints(runs):
         if n <= 1000:
             assert r["floor"] < 1e-7
             assert r["fp32"] < n * 1e-6
-            assert r["fp32_cn64"] < min(n * 1e-6, r["fp32"] / 3)
+            assert r["fp32_cn64"] < min(1e-5, r["fp32"] / 3)
             assert r["fp32_storage"] < 1e-5
         else:
+            # after the collapse the trajectory amplifies any perturbation ~1e4 times: FP32
+            # storage stays at the floor; the FP32-arithmetic row pass of FP32 and FP32-CN64 keeps
+            # adding its rounding in the filament and follows a neighbouring trajectory (measured
+            # 5.5e-2 and 0.09-0.2 at 1e4 steps, floor 2.9e-4): held to 500 and 2000 times the floor
             assert r["fp32_storage"] < 3 * r["floor"] + 1e-5
-            assert np.isfinite(r["fp32"])
+            assert r["fp32_cn64"] < 500 * r["floor"]
+            assert r["fp32"] < 2000 * r["floor"]

@@ -2,7 +2,10 @@
 
 Tolerances: FP64 stages <= 1e-12 relative; FP64 whole runs <= 1e-10 relative in the
 r-weighted norm; FP32 field error <= 1e-5 (the FP32 target), with per-output errors for
-fluence and rho_max.  Inputs are seeded synthetic Gaussians or seeded random fields.
+fluence and rho_max at the same target.  The largest element error over the largest element
+is held to ELEMENTWISE times the field bound: it sits on the axis at the focus, where the
+r-weighted norm gives least weight, and measures 4-9 times the field error in every FP32 mode.
+Inputs are seeded synthetic Gaussians or seeded random fields.
 """
 import math
 import sys
@@ -32,6 +35,9 @@ def werr(a, ref):
     num = np.sum(w[:, None] * np.abs(a - ref) ** 2)
     den = np.sum(w[:, None] * np.abs(ref) ** 2)
     return math.sqrt(num / den)
+
+
+ELEMENTWISE = 10
 
 
 def relmax(a, ref):
@@ -102,11 +108,16 @@ def test_cn_stage_tiles(precision, tiles):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("nt", [64, 256, 2048, 8192])
-@pytest.mark.parametrize("terms", [wl.KERR, wl.ALL_TERMS & ~(wl.DIFFRACTION | wl.GVD)])
+@pytest.mark.parametrize("terms", [wl.KERR, wl.ALL_TERMS & ~(wl.DIFFRACTION | wl.GVD), "kerr_n8"])
 def test_nl_stage(precision, nt, terms):
+    """One nonlinear sub-step (Eq. nonlinearpart) against the oracle: Kerr only, every term, and
+    the whole Kerr sum to j = 4 (n2, n4, n6, n8) with every term."""
     say(f"nl stage {precision} nt={nt} terms={terms}")
     nr = 6
     inst = wl.config_full(nr=nr, nt=nt)
+    if terms == "kerr_n8":
+        inst.update(n6=wl.config_higher_kerr()["n6"], n8=wl.config_higher_kerr()["n8"])
+        terms = wl.ALL_TERMS & ~(wl.DIFFRACTION | wl.GVD)
     inst["terms"] = terms
     rng = np.random.default_rng(nt)
     t = inst["t_min"] + np.arange(nt) * (inst["t_max"] - inst["t_min"]) / nt
@@ -169,23 +180,69 @@ def test_single_step_error(precision):
     assert e < (1e-12 if precision == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_full_physics_reduced_grid(precision):
-    """Full model (Kerr n2+n4, plasma, MPA, collisions) on a reduced grid, 40 steps of 5 mm
-    from the ionising regime (the oracle amplifies a 1e-15 input perturbation to ~3e-14 here).
-    FP64: 1e-10.  FP32: the per-step bound accumulated coherently, 40 x 1e-6 (the FP32
-    rounding errors of a slowly varying field repeat from step to step; measured ~2.4e-5)."""
-    tol = 1e-10 if precision == "fp64" else 40 * 1e-6
+def _full_physics_40(precision):
     inst = wl.config_full(nr=96, nt=512)
-    say(f"full physics {precision}")
     a0 = wl.gaussian_field(inst) * math.sqrt(6e17 / inst["I0"])
-    got, plan = _run(inst, precision, 40, a0=a0)
-    want = oracle.propagate(inst, a0, 40)
-    e = werr(got.astype(np.complex128), want)
+    a_in = a0 if precision == "fp64" else a0.astype(np.complex64)
+    got, plan = _run(inst, precision, 40, a0=a_in)
+    want = oracle.propagate(inst, a_in.astype(np.complex128), 40)
     dg = oracle.diagnostics(inst, want)
     assert dg["rho_max"] > 1e20  # the density term is exercised
-    say(f"  field error {e:.3e}")
-    assert e < tol
+    g = got.astype(np.complex128)
+    d = plan.split_diag(plan.diagnostics(plan.pack(got)))[0]
+    errs = {"field": werr(g, want), "elementwise": relmax(g, want),
+            "fluence": float(np.max(np.abs(d["fluence"] - dg["fluence"])) / np.max(dg["fluence"])),
+            "rho_max": abs(d["rho_max"] / dg["rho_max"] - 1)}
+    say(f"  full physics {precision}, 40 steps: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    return errs
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32_cn64", 1e-5), ("fp32_storage", 1e-5)])
+def test_full_physics_reduced_grid(precision, tol):
+    """Full model (Kerr n2+n4, plasma, MPA, collisions) on a reduced grid, 40 steps of 5 mm
+    from the ionising regime (the oracle amplifies a 1e-15 input perturbation to ~3e-14 here),
+    from the same (FP32-rounded where the field is FP32) input.  Every output within the FP32
+    target of 1e-5 of the oracle for the FP32-field modes that claim it, FP64 within 1e-10:
+    the r-weighted field error, the fluence and the peak density (the largest element error over
+    the largest element within ELEMENTWISE times the bound)."""
+    errs = _full_physics_40(precision)
+    for k, v in errs.items():
+        assert v < (ELEMENTWISE * tol if k == "elementwise" else tol), (k, v)
+
+
+def test_full_physics_reduced_grid_plain_fp32_reported_not_at_target():
+    """Plain FP32 on the same 40 ionising steps is not at the 1e-5 target (its transform and
+    elimination roundings repeat from step to step; measured ~2.4e-5 in the field): the test
+    holds it to the per-step bound 1e-6 accumulated over the 40 steps, and checks that the two
+    precision remedies are both below it."""
+    errs = _full_physics_40("fp32")
+    assert errs["field"] < 40 * 1e-6 and errs["elementwise"] < ELEMENTWISE * 40 * 1e-6
+    assert _full_physics_40("fp32_cn64")["field"] < errs["field"]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32_cn64", 1e-5), ("fp32_storage", 1e-5)])
+def test_higher_order_kerr_and_chirp(precision, tol):
+    """The whole Kerr sum of Eq. nlse (n2, n4, n6, n8 of alternating sign) with plasma, MPA and
+    collisions, from a chirped pulse (Eq. gauss with C = -1.5), 30 steps of 5 mm through the
+    C ABI against the oracle: field, element-wise, fluence and peak density."""
+    inst = wl.config_higher_kerr(nr=96, nt=512)
+    a0 = wl.gaussian_field(inst)
+    assert abs(np.angle(a0[0, 3 * 512 // 8] / a0[0, 256])) > 0.1  # the input is chirped
+    a_in = a0 if precision == "fp64" else a0.astype(np.complex64)
+    got, plan = _run(inst, precision, 30, a0=a_in)
+    want = oracle.propagate(inst, a_in.astype(np.complex128), 30)
+    dg = oracle.diagnostics(inst, want)
+    g = got.astype(np.complex128)
+    d = plan.split_diag(plan.diagnostics(plan.pack(got)))[0]
+    errs = {"field": werr(g, want), "elementwise": relmax(g, want),
+            "fluence": float(np.max(np.abs(d["fluence"] - dg["fluence"])) / np.max(dg["fluence"])),
+            "rho_max": abs(d["rho_max"] / dg["rho_max"] - 1)}
+    # the n6 and n8 terms matter: dropping them moves the oracle's own result far beyond tol
+    off = dict(inst, n6=0.0, n8=0.0)
+    assert werr(oracle.propagate(off, a_in.astype(np.complex128), 30), want) > 1e-3
+    say(f"  higher-order Kerr + chirp {precision}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < (ELEMENTWISE * tol if k == "elementwise" else tol), (k, v)
 
 
 def test_fp64_error_tracks_conditioning_on_unstable_trajectory():
@@ -496,7 +553,7 @@ def test_fp32_storage_single_step_and_run():
     e40_32 = werr(g32.astype(np.complex128), want40)
     say(f"  fp32-storage: one step {e1:.2e}, 40 steps {e40:.2e} (FP32 arithmetic: {e40_32:.2e})")
     assert e1 < 2e-7
-    assert e40 < 1e-5
+    assert e40 < 1e-5  # the FP32 target
     assert e40 < e40_32 / 5
 
 
@@ -589,7 +646,7 @@ def test_fp32_cn64_run_errors_vs_fp64():
         say(f"  {inst['nr']}x{inst['nt']}, {n} steps vs FP64: " + ", ".join(f"{k} {v:.2e}" for k, v in e.items()))
         assert e["fp32_cn64"] < e["fp32"] / 2
         assert e["fp32_storage"] < e["fp32_cn64"]
-        assert e["fp32_cn64"] < n * 1e-6
+        assert e["fp32_cn64"] < 1e-5  # the FP32 target, over the whole run
 
 
 def test_fp32_cn64_batch_and_graph():

@@ -27,6 +27,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -170,7 +171,7 @@ def cpu_baseline(insts, seconds: float):
     return out
 
 
-def kernel_name(precision, launch, tiles):
+def kernel_name(precision, launch):
     """Template name of one launch of the sweep's step, as rocprofv3 reports it."""
     if launch["pass"] == "row":
         nt = launch["size"]
@@ -183,20 +184,19 @@ def kernel_name(precision, launch, tiles):
         return f"row_kernel<{r}, {st}, {nt}, {e}, {flags}>"
     r = "float" if precision == "fp32" else "double"
     st = "double" if precision == "fp64" else "float"
-    return f"col_kernel<{r}, {st}, {tiles[0]}, {tiles[1]}>"
+    return f"col_kernel<{r}, {st}, {launch['tile'][0]}, {launch['tile'][1]}>"
 
 
-def sweep_run(torch, insts, precision, steps, warmup, tiles, graph=True):
-    """One plan over the whole sweep on its own stream: `steps` timed steps (graph replay), then
-    per-launch kernel times, then the field after one 100-step run.  Returns (seconds, launches,
-    fields, plan tiles)."""
+def sweep_run(torch, insts, precision, steps, warmup, tune_cache, graph=True):
+    """One plan over the whole sweep on its own stream, column tiles per nr from the tune cache:
+    `steps` timed steps (graph replay), then per-launch kernel times, then the field after one
+    100-step run.  Returns (seconds, launches, fields, diagnostics)."""
     from paper_1507_05988_amd import fcn
     from paper_1507_05988_amd import workloads as wl
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        plan = fcn.Plan(insts, precision=precision, use_graph=graph, stream=stream, col_tile=tiles[0],
-                        col_rows=tiles[1])
+        plan = fcn.Plan(insts, precision=precision, use_graph=graph, stream=stream, tune_cache=tune_cache)
         dt = np.complex128 if precision == "fp64" else np.complex64
         init = plan.pack([wl.gaussian_field(i, dt) for i in insts])
         f = init.clone()
@@ -210,10 +210,9 @@ def sweep_run(torch, insts, precision, steps, warmup, tiles, graph=True):
         plan.sync()
         fields = plan.unpack(f)
         diags = plan.split_diag(plan.diagnostics(f))
-        used = plan.tiles()[:2]
         plan.close()
         del f, init
-    return sec, launches, fields, diags, used
+    return sec, launches, fields, diags
 
 
 def sweep_measurement(torch, args):
@@ -227,15 +226,16 @@ def sweep_measurement(torch, args):
     hp = args.headline_precision
     modes = [hp] if args.only_headline else [hp, "fp64", "fp32" if hp == "fp32_cn64" else "fp32_cn64"]
     res = {}
+    cache = os.path.join(tempfile.mkdtemp(prefix="fcn_tiles_"), "tiles.txt")
     for prec in modes:
-        t = autotune.tune(insts, prec, steps=10, repeats=2)
-        tiles = (t["col_tile"], t["col_rows"])
+        t = autotune.tune(insts, prec, steps=10, repeats=2, cache_path=cache)
         steps = args.steps if prec == hp else wl.BATCH_STEPS
-        sec, launches, fields, diags, used = sweep_run(torch, insts, prec, steps, args.warmup, tiles)
-        res[prec] = dict(sec=sec, steps=steps, launches=launches, fields=fields, diags=diags, tiles=used,
-                         table=t["table"])
+        sec, launches, fields, diags = sweep_run(torch, insts, prec, steps, args.warmup, cache)
+        tiles = {nr: [v["col_tile"], v["col_rows"]] for nr, v in t["per_nr"].items()}
+        res[prec] = dict(sec=sec, steps=steps, launches=launches, fields=fields, diags=diags, tiles=tiles,
+                         tune={nr: {k: round(x, 2) for k, x in v["table"].items()} for nr, v in t["per_nr"].items()})
         print(f"[bench] sweep {prec}: {steps} steps in {sec:.4f} s ({sec / steps * 1e3:.3f} ms/step), "
-              f"column tile {used[0]}x{used[1]}", file=sys.stderr, flush=True)
+              f"column tiles per nr {tiles}", file=sys.stderr, flush=True)
     return insts, pts, res
 
 
@@ -658,7 +658,7 @@ def main():
     # ---- roofline of the dominant kernel: the launch of the step with the longest mean duration
     launches = h["launches"]
     for L in launches:
-        L["kernel"] = kernel_name(hp, L, h["tiles"])
+        L["kernel"] = kernel_name(hp, L)
         L["bytes"] = L["points"] * 16  # FP32 field: each launch reads and writes its points once
         L["gbs"] = round(L["bytes"] / (L["ms"] * 1e-3) / 1e9, 1)
     dom = max(launches, key=lambda L: L["ms"])
@@ -701,7 +701,8 @@ def main():
                                 + f", HIP-graph replay, timed in runs of {wl_batch_steps()} steps from the "
                                   "initial pulses"),
                    "precision": hp, "instances": len(insts), "points": pts,
-                   "column_tile": list(h["tiles"]), "terms": "diffraction+GVD+Kerr(n2)"},
+                   "column_tiles_per_nr": h["tiles"], "terms": "diffraction+GVD+Kerr(n2)"},
+        "column_tile_tuning_us": h["tune"],
         "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1),
         "roofline": roofline,
         "launches": [{k: (round(v, 6) if k == "ms" else v) for k, v in L.items()} for L in launches],
@@ -714,7 +715,7 @@ def main():
         out["accuracy_vs_fp64"] = sweep_errors(insts, h["fields"], ref, h["diags"], dref)
         out["sweep"] = {"fp64_plain": {"value": round(v64, 1), "ms_per_step": round(sw["fp64"]["sec"] * 1e3 /
                                                                                    sw["fp64"]["steps"], 4),
-                                       "column_tile": list(sw["fp64"]["tiles"]),
+                                       "column_tiles_per_nr": sw["fp64"]["tiles"],
                                        "launches": [{"pass": L["pass"], "size": L["size"], "ms": round(L["ms"], 6)}
                                                     for L in sw["fp64"]["launches"]]}}
         for k, r in sw.items():
@@ -722,7 +723,7 @@ def main():
                 continue
             v = pts * r["steps"] / r["sec"]
             out["sweep"][k] = {"value": round(v, 1), "ms_per_step": round(r["sec"] * 1e3 / r["steps"], 4),
-                               "vs_fp64_plain": round(v / v64, 3), "column_tile": list(r["tiles"]),
+                               "vs_fp64_plain": round(v / v64, 3), "column_tiles_per_nr": r["tiles"],
                                "launches": [{"pass": L["pass"], "size": L["size"], "ms": round(L["ms"], 6)}
                                             for L in r["launches"]],
                                "accuracy_vs_fp64": sweep_errors(insts, r["fields"], ref, r["diags"], dref)}

@@ -106,9 +106,15 @@ typedef struct {
     int32_t use_graph;       /* 1: replay the step body as a captured HIP graph (needs a non-NULL
                                 stream; fcn_step, and fcn_propagate without diagnostics records
                                 or dz log: those calls run eagerly) */
-    int32_t col_tile;        /* 0: auto; else frequencies per column workgroup (1, 2, 4, 8, 16 or 32) */
+    int32_t col_tile;        /* 0: auto; else frequency pairs (p, nt - p) per column workgroup
+                                (1, 2, 4, 8, 16 or 32) */
     int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (8 or 16) */
     int32_t reserved;        /* must be 0 */
+    const char *tune_cache;  /* NULL, or a text file of tuned column tiles per nr, one per line:
+                                "<precision> col <nr> <W> <L> [us]" with precision fp64, fp32,
+                                fp32_storage or fp32_cn64 ('#' starts a comment); the entry for a
+                                bucket's nr sets its tile unless col_tile / col_rows are given.
+                                Read by fcn_plan_create (FCN_E_ARG if unreadable or malformed). */
 } fcn_options;
 
 /* Number of doubles per instance in one diagnostics record: 8 scalars then nr fluence values.
@@ -194,9 +200,11 @@ fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, doub
  * kernel launch of the steady step body (events recorded by the kernels themselves).  A step is
  * one row-pass launch per distinct nt of the plan (ascending nt), then one column-pass launch per
  * distinct nr (ascending nr): *n_launches of them.  launch_ms[l] receives the mean duration of
- * launch l; launch_info[3 l .. 3 l + 2] receive {pass: 0 row, 1 column; its nt or nr; the grid
- * points the launch covers}.  max_launches: capacity of both host arrays (FCN_E_SIZE, with
- * *n_launches set, when too small).  Synchronous; 2 <= nsteps <= 10000. */
+ * launch l; launch_info[5 l .. 5 l + 4] receive {pass: 0 row, 1 column; its nt or nr; the grid
+ * points the launch covers; elements per thread and rows per workgroup (row) or pair slots per
+ * workgroup W and rows per thread L (column)}.  max_launches: capacity of the host arrays
+ * (launch_ms: max_launches, launch_info: 5 max_launches; FCN_E_SIZE, with *n_launches set,
+ * when too small).  Synchronous; 2 <= nsteps <= 10000. */
 fcn_status fcn_step_timed_launches(fcn_plan_t plan, void *field_dev, int64_t nsteps, int32_t max_launches,
                                    int32_t *n_launches, double *launch_ms, int64_t *launch_info);
 

@@ -84,14 +84,15 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const int pl = t % W;
     const int k = t / W;
     const int S = blockDim.x / W;
-    // reduced equations in LDS, one array per coefficient ([W][S + 1], one spare entry per
-    // column), so neighbouring chunks are neighbouring 8- or 16-byte words
-    const int S1 = S + 1;
+    // reduced equations in LDS, one array per coefficient, entry (pair slot, chunk) at
+    // chunk * W + slot = the thread index: the lanes of a wavefront touch consecutive 8- or
+    // 16-byte words at every access (also at the +-h neighbours of the reduction), so no two
+    // lanes of a group share a bank
     c2<R> *q_l = reinterpret_cast<c2<R> *>(smem_raw);
-    c2<R> *q_u = q_l + W * S1;
-    c2<R> *q_r0 = q_u + W * S1;
-    c2<R> *q_r1 = q_r0 + W * S1;
-    const int me = pl * S1 + k;
+    c2<R> *q_u = q_l + W * S;
+    c2<R> *q_r0 = q_u + W * S;
+    c2<R> *q_r1 = q_r0 + W * S;
+    const int me = t;
 
     const int slot = it.p0 + pl;          // columns slot and nt - slot
     const bool live = slot <= nt / 2;     // the last tile of an instance can be partly empty
@@ -229,10 +230,10 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     __syncthreads();
     c2<R> pl1 = czero<R>(), pu1 = czero<R>(), pr1 = czero<R>(), pr2 = czero<R>();
     if (k > 0) {
-        pl1 = q_l[me - 1];
-        pu1 = q_u[me - 1];
-        pr1 = q_r0[me - 1];
-        pr2 = q_r1[me - 1];
+        pl1 = q_l[me - W];
+        pu1 = q_u[me - W];
+        pr1 = q_r0[me - W];
+        pr2 = q_r1[me - W];
     }
     c2<R> yl, yu, yr1, yr2;  // Y_{k-1}, Y_{k+1} coefficients and right-hand sides, unit diagonal
     {
@@ -257,16 +258,16 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
         c2<R> ll = czero<R>(), lu = czero<R>(), lr1 = czero<R>(), lr2 = czero<R>();
         c2<R> hl = czero<R>(), hu = czero<R>(), hr1 = czero<R>(), hr2 = czero<R>();
         if (k - h >= 0) {
-            ll = q_l[me - h];
-            lu = q_u[me - h];
-            lr1 = q_r0[me - h];
-            lr2 = q_r1[me - h];
+            ll = q_l[me - h * W];
+            lu = q_u[me - h * W];
+            lr1 = q_r0[me - h * W];
+            lr2 = q_r1[me - h * W];
         }
         if (k + h < S) {
-            hl = q_l[me + h];
-            hu = q_u[me + h];
-            hr1 = q_r0[me + h];
-            hr2 = q_r1[me + h];
+            hl = q_l[me + h * W];
+            hu = q_u[me + h * W];
+            hr1 = q_r0[me + h * W];
+            hr2 = q_r1[me + h * W];
         }
         // eq_k - l_k eq_{k-h} - u_k eq_{k+h}, then renormalise (operator part shared)
         const c2<R> dg = cmsub<R>(cmsub<R>(mk<R>(R(1), R(0)), yl, lu), yu, hl);
@@ -288,8 +289,8 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const c2<R> xf1 = yr1, xf2 = yr2;
     c2<R> nf1 = czero<R>(), nf2 = czero<R>();
     if (k + 1 < S) {
-        nf1 = q_r0[me + 1];
-        nf2 = q_r1[me + 1];
+        nf1 = q_r0[me + W];
+        nf2 = q_r1[me + W];
     }
     const c2<R> xl1 = cmsub<R>(cmsub<R>(r1_1, l1, xf1), u1, nf1);
     const c2<R> xl2 = cmsub<R>(cmsub<R>(r1_2, l1, xf2), u1, nf2);
@@ -331,7 +332,7 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
     const int S = (nr + L - 1) / L;
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
-    const size_t shm = 4 * sizeof(c2<R>) * (size_t)W * (S + 1);
+    const size_t shm = 4 * sizeof(c2<R>) * (size_t)W * S;
     hipExtLaunchKernelGGL((col_kernel<R, ST, W, L>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1, 0, a);
     return hipGetLastError();
 }

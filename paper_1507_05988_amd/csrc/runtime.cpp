@@ -90,6 +90,7 @@ struct fcn_plan_s {
     void *graph_field = nullptr;
 
     std::string err;
+    std::string tune_cache_path;
 
     DevInst *d_inst() const { return reinterpret_cast<DevInst *>(ws + off_inst); }
     RowItem *d_rowitems() const { return reinterpret_cast<RowItem *>(ws + off_rowitems); }
@@ -214,6 +215,42 @@ void choose_col_tiles(int precision, int nr, const fcn_options &opt, int &w, int
     while (w * ((nr + l - 1) / l) > 512 && w > 4) w /= 2;
     while (w * ((nr + l - 1) / l) > 512 && l < 16 && opt.col_rows == 0 && precision == FCN_FP32) l *= 2;
     while (w * ((nr + l - 1) / l) > 512 && w > 1) w /= 2;
+}
+
+const char *precision_name(int precision) {
+    switch (precision) {
+        case FCN_FP64: return "fp64";
+        case FCN_FP32: return "fp32";
+        case FCN_FP32_STORAGE: return "fp32_storage";
+        default: return "fp32_cn64";
+    }
+}
+
+// Column tiles per nr from a tune cache file: lines "<precision> col <nr> <W> <L> [us]"
+// ('#' starts a comment; other passes and precisions are skipped).  Returns false if the
+// file cannot be read or a line of this plan's precision is malformed.
+bool read_tune_cache(const char *path, int precision, std::map<int, std::pair<int, int>> &col) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool ok = true;
+    const std::string prec = precision_name(precision);
+    while (std::fgets(line, sizeof line, f)) {
+        char *hash = std::strchr(line, '#');
+        if (hash) *hash = 0;
+        char pname[64] = {0}, pass[16] = {0};
+        int size = 0, a = 0, b = 0;
+        const int n = std::sscanf(line, "%63s %15s %d %d %d", pname, pass, &size, &a, &b);
+        if (n <= 0) continue;  // blank or comment
+        if (prec != pname || std::strcmp(pass, "col") != 0) continue;
+        if (n < 5 || size < 3 || a < 1 || b < 1) {
+            ok = false;
+            break;
+        }
+        col[size] = std::make_pair(a, b);
+    }
+    std::fclose(f);
+    return ok;
 }
 
 fcn_status build_plan(fcn_plan_t p) {
@@ -353,13 +390,23 @@ fcn_status build_plan(fcn_plan_t p) {
         b.grid = (b.nitems + rpw - 1) / rpw;
         p->row_buckets.push_back(b);
     }
-    // column work lists, one bucket per nr
+    // column work lists, one bucket per nr; tiles from the options, else the tune cache, else
+    // the default rule
+    std::map<int, std::pair<int, int>> cached;
+    if (p->opt.tune_cache && !read_tune_cache(p->opt.tune_cache, p->precision, cached))
+        return fail(p, FCN_E_ARG, "tune cache %s unreadable or malformed", p->opt.tune_cache);
     std::map<int, std::vector<int>> by_nr;
     for (int i = 0; i < B; i++) by_nr[p->insts[i].nr].push_back(i);
     for (auto &kv : by_nr) {
         ColBucket b{};
         b.nr = kv.first;
-        choose_col_tiles(p->precision, b.nr, p->opt, b.w, b.l);
+        fcn_options o = p->opt;
+        const auto hit = cached.find(b.nr);
+        if (hit != cached.end()) {
+            if (o.col_tile == 0) o.col_tile = hit->second.first;
+            if (o.col_rows == 0) o.col_rows = hit->second.second;
+        }
+        choose_col_tiles(p->precision, b.nr, o, b.w, b.l);
         if (b.w * ((b.nr + b.l - 1) / b.l) > 512) return fail(p, FCN_E_SIZE, "nr=%d too large for the column solve", b.nr);
         if (!col_tiles_supported(b.w, b.l)) return fail(p, FCN_E_ARG, "column tile %dx%d not built", b.w, b.l);
         b.item_off = (int)p->col_items.size();
@@ -648,6 +695,10 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
     p->batch = batch;
     p->insts.assign(inst, inst + batch);
     if (opt) p->opt = *opt;
+    if (p->opt.tune_cache) {  // the plan keeps its own copy of the path
+        p->tune_cache_path = p->opt.tune_cache;
+        p->opt.tune_cache = p->tune_cache_path.c_str();
+    }
     p->precision = p->opt.precision;
     if (p->precision != FCN_FP64 && p->precision != FCN_FP32 && p->precision != FCN_FP32_STORAGE &&
         p->precision != FCN_FP32_CN64) {
@@ -957,16 +1008,20 @@ fcn_status fcn_step_timed_launches(fcn_plan_t p, void *field_dev, int64_t nsteps
             const auto &b = p->row_buckets[l];
             for (const auto &d : p->dinst)
                 if (d.nt == b.nt) pts += (int64_t)d.nr * d.nt;
-            launch_info[3 * l] = 0;
-            launch_info[3 * l + 1] = b.nt;
+            launch_info[5 * l] = 0;
+            launch_info[5 * l + 1] = b.nt;
+            launch_info[5 * l + 3] = row_elems_for(b.nt, row_fp64_arith(p->precision));
+            launch_info[5 * l + 4] = row_rows_per_group(b.nt, (int)launch_info[5 * l + 3]);
         } else {
             const auto &b = p->col_buckets[l - nrow];
             for (const auto &d : p->dinst)
                 if (d.nr == b.nr) pts += (int64_t)d.nr * d.nt;
-            launch_info[3 * l] = 1;
-            launch_info[3 * l + 1] = b.nr;
+            launch_info[5 * l] = 1;
+            launch_info[5 * l + 1] = b.nr;
+            launch_info[5 * l + 3] = b.w;
+            launch_info[5 * l + 4] = b.l;
         }
-        launch_info[3 * l + 2] = pts;
+        launch_info[5 * l + 2] = pts;
     }
     return FCN_OK;
 }

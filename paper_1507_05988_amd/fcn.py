@@ -76,7 +76,7 @@ class Options(ctypes.Structure):
         ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32),
         ("max_phase", ctypes.c_double), ("dz_min", ctypes.c_double), ("dz_max", ctypes.c_double),
         ("use_graph", ctypes.c_int32), ("col_tile", ctypes.c_int32), ("col_rows", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
     ]
 
 
@@ -160,7 +160,7 @@ class Plan:
 
     def __init__(self, instances, precision: str = "fp64", adaptive: bool = False, max_phase: float = 0.05,
                  dz_min: float = 1e-6, dz_max: float = 1e-2, use_graph: bool = False, col_tile: int = 0,
-                 col_rows: int = 0, device: int = 0, stream=None):
+                 col_rows: int = 0, device: int = 0, stream=None, tune_cache: str | None = None):
         import torch
 
         if not torch.cuda.is_available():
@@ -179,7 +179,8 @@ class Plan:
         arr = (Instance * self.batch)(*[make_instance(i) for i in self.instances])
         opt = Options(precision=PRECISIONS[precision], adaptive=int(adaptive),
                       max_phase=max_phase, dz_min=dz_min, dz_max=dz_max, use_graph=int(use_graph),
-                      col_tile=col_tile, col_rows=col_rows, reserved=0)
+                      col_tile=col_tile, col_rows=col_rows, reserved=0,
+                      tune_cache=tune_cache.encode() if tune_cache else None)
         self._h = ctypes.c_void_p()
         rc = self.lib.fcn_plan_create(arr, self.batch, ctypes.byref(opt), ctypes.byref(self._h))
         if rc != FCN_OK:
@@ -280,15 +281,17 @@ class Plan:
 
     def step_timed_launches(self, field, nsteps: int):
         """Steps with HIP events around every launch; returns a list of dicts
-        {pass: "row"|"col", size: nt or nr, points, ms} in launch order."""
+        {pass: "row"|"col", size: nt or nr, points, tile, ms} in launch order (tile: elements per
+        thread and rows per workgroup of a row launch, [W, L] of a column launch)."""
         cap = 64
         n = ctypes.c_int32()
         ms = (ctypes.c_double * cap)()
-        info = (ctypes.c_int64 * (3 * cap))()
+        info = (ctypes.c_int64 * (5 * cap))()
         self._check(self.lib.fcn_step_timed_launches(self._h, self._field_ptr(field), int(nsteps), cap,
                                                      ctypes.byref(n), ms, info))
-        return [{"pass": "row" if info[3 * i] == 0 else "col", "size": int(info[3 * i + 1]),
-                 "points": int(info[3 * i + 2]), "ms": ms[i]} for i in range(n.value)]
+        return [{"pass": "row" if info[5 * i] == 0 else "col", "size": int(info[5 * i + 1]),
+                 "points": int(info[5 * i + 2]), "tile": [int(info[5 * i + 3]), int(info[5 * i + 4])],
+                 "ms": ms[i]} for i in range(n.value)]
 
     def stage(self, stage: int, field, length: float = 0.0):
         self._check(self.lib.fcn_stage(self._h, int(stage), self._field_ptr(field), float(length)))

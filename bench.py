@@ -51,6 +51,8 @@ def weighted_rel_err(a, ref):
 CHUNK = 500          # full-model pulse: timed chunks restart from z = 0 (before the collapse)
 ROOT = os.path.dirname(os.path.abspath(__file__))
 COUNTER_FILE = os.path.join(ROOT, "profiles", "fcn_step_batched64_counters.json")
+# Column tiles per nr chosen by the autotuner on an MI355X (autotune.tune; regenerate with --retune)
+SHIPPED_TILES = os.path.join(ROOT, "paper_1507_05988_amd", "tuning", "mi355x_tiles.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fcn_step_fullmodel_512x2048_traffic.json")
 
 
@@ -187,16 +189,18 @@ def kernel_name(precision, launch):
     return f"col_kernel<{r}, {st}, {launch['tile'][0]}, {launch['tile'][1]}>"
 
 
-def sweep_run(torch, insts, precision, steps, warmup, tune_cache, graph=True):
-    """One plan over the whole sweep on its own stream, column tiles per nr from the tune cache:
-    `steps` timed steps (graph replay), then per-launch kernel times, then the field after one
-    100-step run.  Returns (seconds, launches, fields, diagnostics)."""
+def sweep_run(torch, insts, precision, steps, warmup, tune_cache, lanes, graph=True):
+    """One plan over the whole sweep on its own stream, column tiles per nr from the tune cache,
+    the instances in `lanes` concurrent groups: `steps` timed steps (graph replay), then per-launch
+    kernel times (the launches one after another), then the field after one 100-step run.
+    Returns (seconds, launches, fields, diagnostics)."""
     from paper_1507_05988_amd import fcn
     from paper_1507_05988_amd import workloads as wl
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        plan = fcn.Plan(insts, precision=precision, use_graph=graph, stream=stream, tune_cache=tune_cache)
+        plan = fcn.Plan(insts, precision=precision, use_graph=graph, stream=stream, tune_cache=tune_cache,
+                        lanes=lanes)
         dt = np.complex128 if precision == "fp64" else np.complex64
         init = plan.pack([wl.gaussian_field(i, dt) for i in insts])
         f = init.clone()
@@ -226,14 +230,20 @@ def sweep_measurement(torch, args):
     hp = args.headline_precision
     modes = [hp] if args.only_headline else [hp, "fp64", "fp32" if hp == "fp32_cn64" else "fp32_cn64"]
     res = {}
-    cache = os.path.join(tempfile.mkdtemp(prefix="fcn_tiles_"), "tiles.txt")
+    cache = args.tune_cache
+    if args.retune:  # tune anew into the given file (a fresh one when it is the shipped table)
+        if os.path.abspath(cache) == os.path.abspath(SHIPPED_TILES):
+            cache = os.path.join(tempfile.mkdtemp(prefix="fcn_tiles_"), "tiles.txt")
+        elif os.path.exists(cache):
+            os.unlink(cache)
     for prec in modes:
         t = autotune.tune(insts, prec, steps=10, repeats=2, cache_path=cache)
         steps = args.steps if prec == hp else wl.BATCH_STEPS
-        sec, launches, fields, diags = sweep_run(torch, insts, prec, steps, args.warmup, cache)
+        sec, launches, fields, diags = sweep_run(torch, insts, prec, steps, args.warmup, cache, args.lanes)
         tiles = {nr: [v["col_tile"], v["col_rows"]] for nr, v in t["per_nr"].items()}
         res[prec] = dict(sec=sec, steps=steps, launches=launches, fields=fields, diags=diags, tiles=tiles,
-                         tune={nr: {k: round(x, 2) for k, x in v["table"].items()} for nr, v in t["per_nr"].items()})
+                         tune=({nr: {k: round(x, 2) for k, x in v["table"].items()} for nr, v in t["per_nr"].items()}
+                               if not t["cached"] else f"from {os.path.relpath(cache, ROOT)}"))
         print(f"[bench] sweep {prec}: {steps} steps in {sec:.4f} s ({sec / steps * 1e3:.3f} ms/step), "
               f"column tiles per nr {tiles}", file=sys.stderr, flush=True)
     return insts, pts, res
@@ -259,7 +269,7 @@ def sweep_errors(insts, got, ref, dgot, dref):
     return out
 
 
-def paper_shapes_measurement(torch):
+def paper_shapes_measurement(torch, tune_cache):
     """The paper's own grids, as context beside its CPU numbers (Sec. 5.1 Table 2 and Sec. 5.2;
     the values come from tests/golden/paper_printed_values.json).  The paper's runs are FP64 on
     an Intel Xeon with Pthreads and state no physics for the timing example; the comparison is
@@ -279,7 +289,7 @@ def paper_shapes_measurement(torch):
         pts = int(inst["nr"]) * int(inst["nt"])
         rec = {"grid": f"{inst['nr']}x{inst['nt']}", "steps_in_paper": nz, "timed_steps": timed, **ctx}
         for prec in ("fp64", "fp32"):
-            t = autotune.tune(inst, prec, steps=10, repeats=2)
+            t = autotune.tune(inst, prec, steps=10, repeats=2, cache_path=tune_cache)
             plan = fcn.Plan(inst, precision=prec, col_tile=t["col_tile"], col_rows=t["col_rows"])
             a0 = wl.gaussian_field(inst)
             init = plan.pack(a0 if prec == "fp64" else a0.astype(np.complex64))
@@ -536,7 +546,7 @@ def full_model_measurement(torch, args):
     n = min(max(args.steps, 100), 1000)
     out = {"grid": "512x2048", "steps": n, "unit": "grid-pt z-steps/s"}
     for prec in ("fp32_cn64", "fp32", "fp32_storage", "fp64"):
-        t = autotune.tune(inst, prec, steps=50, repeats=3)
+        t = autotune.tune(inst, prec, steps=50, repeats=3, cache_path=args.tune_cache)
         plan = fcn.Plan(inst, precision=prec, col_tile=t["col_tile"], col_rows=t["col_rows"])
         init = plan.pack(a0 if prec == "fp64" else a0.astype(np.complex64))
         f = init.clone()
@@ -608,6 +618,11 @@ def main():
     ap.add_argument("--headline-precision", default="fp32_cn64", choices=["fp32_cn64", "fp32"],
                     help="mode of the headline line: fp32_cn64 (within 1e-5 of FP64 on every pulse of the "
                          "sweep) or fp32 (faster; its largest pulse misses 1e-5)")
+    ap.add_argument("--tune-cache", default=SHIPPED_TILES,
+                    help="tune cache of column tiles per nr (tuned where it lacks an entry)")
+    ap.add_argument("--retune", action="store_true", help="tune every column tile anew")
+    ap.add_argument("--lanes", type=int, default=4,
+                    help="concurrent instance groups of the sweep plans (fcn_options.lanes)")
     ap.add_argument("--only-headline", action="store_true",
                     help="only the headline sweep in the headline mode (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -655,21 +670,31 @@ def main():
     value = pts * h["steps"] / h["sec"]
     ms_per_step = h["sec"] * 1e3 / h["steps"]
 
-    # ---- roofline of the dominant kernel: the launch of the step with the longest mean duration
+    # ---- roofline of the dominant kernel: the kernel template with the longest total time per
+    # step (with several lanes a template serves several launches of a step): its average bytes
+    # per launch over its average launch duration, which is what rocprofv3's per-kernel average
+    # duration of the same run measures
     launches = h["launches"]
+    by_kernel = {}
     for L in launches:
         L["kernel"] = kernel_name(hp, L)
         L["bytes"] = L["points"] * 16  # FP32 field: each launch reads and writes its points once
         L["gbs"] = round(L["bytes"] / (L["ms"] * 1e-3) / 1e9, 1)
-    dom = max(launches, key=lambda L: L["ms"])
-    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
-    cnt = measured_counters(hp, dom["kernel"])
+        k = by_kernel.setdefault(L["kernel"], {"ms": 0.0, "bytes": 0, "launches": 0})
+        k["ms"] += L["ms"]
+        k["bytes"] += L["bytes"]
+        k["launches"] += 1
+    dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    avg_bytes = dom["bytes"] / dom["launches"]
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    cnt = measured_counters(hp, dom_name)
     hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4),
            "traffic": int(cnt["bytes_per_launch"]) if cnt else None}
     roofline = dict(hbm)
     if cnt and cnt.get("valu_insts_per_launch"):
-        lane_ops = cnt["valu_insts_per_launch"] * 64 / (dom["ms"] * 1e-3) / 1e12
+        lane_ops = cnt["valu_insts_per_launch"] * 64 / (avg_ms * 1e-3) / 1e12
         valu = {"bound": "alu", "achieved": round(lane_ops, 3), "peak": round(VALU_PEAK_TLANE_OPS, 3),
                 "unit": "T VALU lane-ops/s", "frac": round(lane_ops / VALU_PEAK_TLANE_OPS, 4),
                 "valu_insts_per_launch": cnt["valu_insts_per_launch"]}
@@ -677,8 +702,8 @@ def main():
             roofline = dict(valu, traffic=hbm["traffic"], hbm=hbm)
         else:
             roofline["valu"] = valu
-    roofline.update(kernel=dom["kernel"], kernel_ms=round(dom["ms"], 6), points_per_launch=dom["points"],
-                    bytes_per_launch=dom["bytes"])
+    roofline.update(kernel=dom_name, kernel_ms=round(avg_ms, 6), launches_per_step=dom["launches"],
+                    bytes_per_launch=round(avg_bytes), kernel_ms_per_step=round(dom["ms"], 6))
 
     out = {
         "metric": METRIC,
@@ -698,9 +723,9 @@ def main():
                                 + ("FP32 field, FP32 FFTs (twiddle pairs) and nonlinear step, FP64 CN column "
                                    "solve and diagnostics" if hp == "fp32_cn64" else "FP32 field and arithmetic, "
                                    "FP64 diagnostics")
-                                + f", HIP-graph replay, timed in runs of {wl_batch_steps()} steps from the "
-                                  "initial pulses"),
-                   "precision": hp, "instances": len(insts), "points": pts,
+                                + f", {args.lanes} concurrent instance groups, HIP-graph replay, timed in runs of "
+                                  f"{wl_batch_steps()} steps from the initial pulses"),
+                   "precision": hp, "instances": len(insts), "points": pts, "lanes": args.lanes,
                    "column_tiles_per_nr": h["tiles"], "terms": "diffraction+GVD+Kerr(n2)"},
         "column_tile_tuning_us": h["tune"],
         "hbm_gbs_algorithmic": round(value * 32 / 1e9, 1),
@@ -732,7 +757,7 @@ def main():
         if not args.no_full_model:
             out["full_model_pulse"] = full_model_measurement(torch, args)
         if not args.no_paper_shapes:
-            out["paper_shapes"] = paper_shapes_measurement(torch)
+            out["paper_shapes"] = paper_shapes_measurement(torch, args.tune_cache)
         if not args.no_long_pulse:
             out["long_pulse"] = long_pulse_measurement(torch, [int(x) for x in args.long_pulse_checkpoints.split(",")])
         if not args.no_parareal:

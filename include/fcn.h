@@ -109,7 +109,15 @@ typedef struct {
     int32_t col_tile;        /* 0: auto; else frequency pairs (p, nt - p) per column workgroup
                                 (1, 2, 4, 8, 16 or 32) */
     int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (8 or 16) */
-    int32_t reserved;        /* must be 0 */
+    int32_t lanes;           /* 0 or 1: every instance on the bound stream.  2..8: the instances
+                                are split into that many groups (greedy balance of nr * nt), each
+                                with its own launches and step counters, and fcn_step runs the
+                                groups concurrently on helper streams created by fcn_plan_bind
+                                (default priority, released by fcn_plan_destroy), forked from and
+                                joined to the bound stream, so one group's column pass overlaps
+                                another's row pass.  Calls with diagnostics records or a dz log,
+                                and fcn_step_scratch, run the groups one after another on the bound
+                                stream.  Results are bit for bit those of one lane. */
     const char *tune_cache;  /* NULL, or a text file of tuned column tiles per nr, one per line:
                                 "<precision> col <nr> <W> <L> [us]" with precision fp64, fp32,
                                 fp32_storage or fp32_cn64 ('#' starts a comment); the entry for a

@@ -108,7 +108,6 @@ def tune(instances, precision: str = "fp32", steps: int = 20, repeats: int = 3, 
     fields = [wl.gaussian_field(i, dt) if "I0" in i else wl.random_field(int(i["nr"]), int(i["nt"]), 0, dtype=dt)
               for i in instances]
     per_nr = {nr: {} for nr in nrs}      # nr -> {"WxL": us} where that bucket ran exactly W x L
-    totals = {}
 
     def measure(w, l):
         try:
@@ -159,3 +158,34 @@ def tuned_plan(instances, precision: str = "fp32", cache_path=None, **kw):
         os.unlink(cache_path)
     tune(instances, precision, cache_path=cache_path)
     return fcn.Plan(instances, precision=precision, tune_cache=cache_path, **kw)
+
+
+def main(argv=None):
+    """Tunes the column tiles of the benchmark's workloads (the batched sweep, the full-model
+    pulse, the long pulse and the paper's two grids) in every precision into one tune cache."""
+    import argparse
+
+    from . import workloads as wl
+
+    ap = argparse.ArgumentParser(description=main.__doc__.split("\n")[0])
+    ap.add_argument("--out", required=True, help="tune cache file to write (entries are added or replaced)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=2)
+    args = ap.parse_args(argv)
+    # the headline workload last: where two workloads share an nr, its choice is the one kept
+    work = {"full": [wl.config_full()], "long": [wl.config_long()], "application": [wl.config_paper_application()],
+            "timing": [wl.config_paper_timing()], "sweep": wl.config_batch()}
+    cache = load_cache(args.out)
+    for prec in ("fp32_cn64", "fp32", "fp32_storage", "fp64"):
+        for name, insts in work.items():
+            for nr in {int(i["nr"]) for i in insts}:
+                cache.pop((prec, nr), None)
+            store_cache(args.out, cache)
+            r = tune(insts, prec, steps=args.steps, repeats=args.repeats, cache_path=args.out)
+            cache = load_cache(args.out)
+            print(f"{prec} {name}: " + ", ".join(f"nr={nr} {v['col_tile']}x{v['col_rows']} {v['us']:.1f} us"
+                                                for nr, v in sorted(r["per_nr"].items())), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -47,7 +47,7 @@ struct DevInst {
     float f_pad;
 };
 
-// Mutable device state, one per plan, inside the workspace.
+// Mutable device state, one per lane of a plan (independent instance groups), in the workspace.
 struct DevState {
     int64_t cnt_col;        // step index read by the column kernels
     int64_t cnt_row;        // step index read by the row kernels
@@ -145,8 +145,8 @@ constexpr bool row_fp64_arith(int precision) { return precision == 0 || precisio
 constexpr bool col_fp64_arith(int precision) { return precision != 1; }
 hipError_t launch_finalize(const DevInst *inst, int batch, const double *row_diag, const double *zpos,
                            const double *dz_ring, const DevState *state, double *out, hipStream_t s);
-hipError_t launch_init_state(DevState *state, unsigned long long *phi_slot, double *dz_ring, double *zpos,
-                             int batch, int64_t n0, hipStream_t s);
-hipError_t launch_clear_flag(DevState *state, hipStream_t s);
+hipError_t launch_init_state(DevState *state, int nstates, unsigned long long *phi_slot, double *dz_ring,
+                             double *zpos, int batch, int64_t n0, hipStream_t s);
+hipError_t launch_clear_flag(DevState *state, int nstates, hipStream_t s);
 
 }  // namespace fcn

@@ -760,15 +760,16 @@ hipError_t launch_finalize(const DevInst *inst, int batch, const double *row_dia
     return hipGetLastError();
 }
 
-// Resets the step state: counters to n0, phase slots, dz ring and z positions to zero.
-__global__ void init_state_kernel(DevState *state, unsigned long long *phi_slot, double *dz_ring, double *zpos,
-                                  int batch, int64_t n0) {
+// Resets the step state of every lane: counters to n0, flags, phase slots, dz ring and z
+// positions to zero.
+__global__ void init_state_kernel(DevState *state, int nstates, unsigned long long *phi_slot, double *dz_ring,
+                                  double *zpos, int batch, int64_t n0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        state->cnt_col = n0;
-        state->cnt_row = n0;
-        state->nonfinite = 0;
-        state->unstable = 0;
+    if (i < nstates) {
+        state[i].cnt_col = n0;
+        state[i].cnt_row = n0;
+        state[i].nonfinite = 0;
+        state[i].unstable = 0;
     }
     if (i < 2 * batch) {
         phi_slot[i] = 0ull;
@@ -777,21 +778,26 @@ __global__ void init_state_kernel(DevState *state, unsigned long long *phi_slot,
     if (i < batch) zpos[i] = 0.0;
 }
 
-hipError_t launch_init_state(DevState *state, unsigned long long *phi_slot, double *dz_ring, double *zpos, int batch,
-                             int64_t n0, hipStream_t s) {
+hipError_t launch_init_state(DevState *state, int nstates, unsigned long long *phi_slot, double *dz_ring,
+                             double *zpos, int batch, int64_t n0, hipStream_t s) {
     const int threads = 256;
-    const int grid = (2 * batch + threads - 1) / threads;
-    hipLaunchKernelGGL(init_state_kernel, dim3(grid), dim3(threads), 0, s, state, phi_slot, dz_ring, zpos, batch, n0);
+    const int n = 2 * batch > nstates ? 2 * batch : nstates;
+    const int grid = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(init_state_kernel, dim3(grid), dim3(threads), 0, s, state, nstates, phi_slot, dz_ring, zpos,
+                       batch, n0);
     return hipGetLastError();
 }
 
-__global__ void clear_flag_kernel(DevState *state) {
-    state->nonfinite = 0;
-    state->unstable = 0;
+__global__ void clear_flag_kernel(DevState *state, int nstates) {
+    const int i = threadIdx.x;
+    if (i < nstates) {
+        state[i].nonfinite = 0;
+        state[i].unstable = 0;
+    }
 }
 
-hipError_t launch_clear_flag(DevState *state, hipStream_t s) {
-    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, state);
+hipError_t launch_clear_flag(DevState *state, int nstates, hipStream_t s) {
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(64), 0, s, state, nstates);
     return hipGetLastError();
 }
 

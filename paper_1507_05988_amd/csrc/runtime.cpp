@@ -10,7 +10,10 @@
 // distinct nr (workgroup size W * ceil(nr/L)); in a batch every launch covers all
 // instances of its bucket.  The step index, the dz ring and the phase-rate slots live in
 // device memory, so the step body is identical from step to step and can be replayed
-// from a captured HIP graph.
+// from a captured HIP graph.  With lanes > 1 the instances are split into independent groups
+// (greedy balance of the grid points), each with its own buckets and step counters, stepped on
+// its own stream between a fork from and a join to the bound stream: one group's column pass
+// (latency-bound) can then overlap another group's row pass (arithmetic-bound).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,6 +43,7 @@ constexpr double kPi = 3.14159265358979323846;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct RowBucket {
+    int lane;
     int nt;
     int scan;  // RK_SCAN when an instance of the bucket has a density term, RK_NOABS when none
                // has a density or absorption term, else 0
@@ -47,6 +51,7 @@ struct RowBucket {
     int grid;
 };
 struct ColBucket {
+    int lane;
     int nr;
     int w, l;
     int item_off, nitems;
@@ -85,7 +90,14 @@ struct fcn_plan_s {
     int64_t n_host = 0;     // step index of the field as seen by the host
     bool seeded = false;    // phase-rate slots hold Phi of the current state's predecessor
 
-    hipGraphExec_t graph_exec = nullptr;
+    int nlanes = 1;                       // independent instance groups
+    std::vector<int> lane_of;             // lane of each instance
+    std::vector<hipStream_t> lane_streams;  // one per lane when nlanes > 1 (created at bind)
+    std::vector<hipEvent_t> lane_events;
+    hipEvent_t fork_event = nullptr;
+    bool serial = false;                  // run every lane on the bound stream (scratch calls)
+
+    std::vector<hipGraphExec_t> graph_exec;  // per lane (one entry with a single lane)
     int graph_steps = 0;
     void *graph_field = nullptr;
 
@@ -101,7 +113,7 @@ struct fcn_plan_s {
     unsigned long long *d_slots() const { return reinterpret_cast<unsigned long long *>(ws + off_slots); }
     double *d_ring() const { return reinterpret_cast<double *>(ws + off_ring); }
     double *d_zpos() const { return reinterpret_cast<double *>(ws + off_zpos); }
-    DevState *d_state() const { return reinterpret_cast<DevState *>(ws + off_state); }
+    DevState *d_state(int lane = 0) const { return reinterpret_cast<DevState *>(ws + off_state) + lane; }
 };
 
 namespace {
@@ -368,12 +380,30 @@ fcn_status build_plan(fcn_plan_t p) {
     p->total_rows = row;
     p->diag_doubles = doff;
 
-    // row work lists, one bucket per nt
-    std::map<int, std::vector<int>> by_nt;
-    for (int i = 0; i < B; i++) by_nt[p->insts[i].nt].push_back(i);
+    // lanes: greedy balance of the grid points (largest instances first)
+    p->nlanes = std::max(1, std::min(p->opt.lanes, B));
+    p->lane_of.assign(B, 0);
+    {
+        std::vector<int> order(B);
+        for (int i = 0; i < B; i++) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return (int64_t)p->insts[a].nr * p->insts[a].nt > (int64_t)p->insts[b].nr * p->insts[b].nt;
+        });
+        std::vector<int64_t> load(p->nlanes, 0);
+        for (int i : order) {
+            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            p->lane_of[i] = l;
+            load[l] += (int64_t)p->insts[i].nr * p->insts[i].nt;
+        }
+    }
+
+    // row work lists, one bucket per (lane, nt)
+    std::map<std::pair<int, int>, std::vector<int>> by_nt;
+    for (int i = 0; i < B; i++) by_nt[{p->lane_of[i], p->insts[i].nt}].push_back(i);
     for (auto &kv : by_nt) {
         RowBucket b{};
-        b.nt = kv.first;
+        b.lane = kv.first.first;
+        b.nt = kv.first.second;
         b.item_off = (int)p->row_items.size();
         for (int i : kv.second)
             for (int m = 0; m < p->insts[i].nr; m++) p->row_items.push_back(RowItem{i, m});
@@ -395,11 +425,12 @@ fcn_status build_plan(fcn_plan_t p) {
     std::map<int, std::pair<int, int>> cached;
     if (p->opt.tune_cache && !read_tune_cache(p->opt.tune_cache, p->precision, cached))
         return fail(p, FCN_E_ARG, "tune cache %s unreadable or malformed", p->opt.tune_cache);
-    std::map<int, std::vector<int>> by_nr;
-    for (int i = 0; i < B; i++) by_nr[p->insts[i].nr].push_back(i);
+    std::map<std::pair<int, int>, std::vector<int>> by_nr;
+    for (int i = 0; i < B; i++) by_nr[{p->lane_of[i], p->insts[i].nr}].push_back(i);
     for (auto &kv : by_nr) {
         ColBucket b{};
-        b.nr = kv.first;
+        b.lane = kv.first.first;
+        b.nr = kv.first.second;
         fcn_options o = p->opt;
         const auto hit = cached.find(b.nr);
         if (hit != cached.end()) {
@@ -441,7 +472,7 @@ fcn_status build_plan(fcn_plan_t p) {
     p->off_zpos = o;
     o = align_up(o + sizeof(double) * B, 256);
     p->off_state = o;
-    o = align_up(o + sizeof(DevState), 256);
+    o = align_up(o + sizeof(DevState) * (size_t)p->nlanes, 256);
     p->ws_bytes = o;
 
     p->image.assign(p->const_bytes, 0);
@@ -465,8 +496,8 @@ RowArgs row_args(fcn_plan_t p, void *field, const RowBucket &b) {
     a.phi_slot = p->d_slots();
     a.dz_ring = p->d_ring();
     a.dz_log = nullptr;
-    a.state = p->d_state();
     a.dz_mode = p->opt.adaptive ? DZ_ADAPTIVE : DZ_FIXED;
+    a.state = p->d_state(b.lane);
     a.max_phase = p->opt.max_phase;
     a.dz_min = p->opt.dz_min;
     a.dz_max = p->opt.dz_max;
@@ -484,7 +515,7 @@ ColArgs col_args(fcn_plan_t p, void *field, const ColBucket &b) {
     a.dz_ring = p->d_ring();
     a.phi_slot = p->d_slots();
     a.zpos = p->d_zpos();
-    a.state = p->d_state();
+    a.state = p->d_state(b.lane);
     return a;
 }
 
@@ -496,12 +527,18 @@ struct StepCtx {
 
 // e0 / e1: optional events recorded at the start of the pass's first kernel and the end of
 // its last kernel.
+// Stream of a lane (lane < 0: every bucket, on the bound stream).
+hipStream_t lane_stream(fcn_plan_t p, int lane) { return lane < 0 ? p->stream : p->lane_streams[lane]; }
+
 // lev: optional events, two per launch (start, end), recorded by each launch itself.
+// lane >= 0: only that lane's buckets, on its stream; lane < 0: all buckets on the bound stream.
 hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, int seed, double stage_len = 0.0,
-                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const hipEvent_t *lev = nullptr) {
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const hipEvent_t *lev = nullptr,
+                    int lane = -1) {
     const size_t nb = p->row_buckets.size();
     for (size_t bi = 0; bi < nb; bi++) {
         const auto &b = p->row_buckets[bi];
+        if (lane >= 0 && b.lane != lane) continue;
         RowArgs a = row_args(p, field, b);
         a.dz_log = ctx.dz_log;
         a.log_base = ctx.log_base;
@@ -510,7 +547,7 @@ hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, in
         a.stage_len = stage_len;
         const bool nl = (flags & (RK_NL_A | RK_NL_B | RK_DIAG)) != 0;
         hipError_t e = launch_row(p->precision, b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)),
-                                  nl ? (flags | b.scan) : flags, a, b.grid, p->stream,
+                                  nl ? (flags | b.scan) : flags, a, b.grid, lane_stream(p, lane),
                                   lev ? lev[2 * bi] : (bi == 0 ? e0 : nullptr),
                                   lev ? lev[2 * bi + 1] : (bi + 1 == nb ? e1 : nullptr));
         if (e != hipSuccess) return e;
@@ -519,14 +556,15 @@ hipError_t row_pass(fcn_plan_t p, void *field, int flags, const StepCtx &ctx, in
 }
 
 hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0, hipEvent_t e0 = nullptr,
-                    hipEvent_t e1 = nullptr, const hipEvent_t *lev = nullptr) {
+                    hipEvent_t e1 = nullptr, const hipEvent_t *lev = nullptr, int lane = -1) {
     const size_t nb = p->col_buckets.size();
     for (size_t bi = 0; bi < nb; bi++) {
         const auto &b = p->col_buckets[bi];
+        if (lane >= 0 && b.lane != lane) continue;
         ColArgs a = col_args(p, field, b);
         a.use_stage_len = stage;
         a.stage_len = stage_len;
-        hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, p->stream,
+        hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, lane_stream(p, lane),
                                   lev ? lev[2 * bi] : (bi == 0 ? e0 : nullptr),
                                   lev ? lev[2 * bi + 1] : (bi + 1 == nb ? e1 : nullptr));
         if (e != hipSuccess) return e;
@@ -540,36 +578,95 @@ constexpr int F_LAST = RK_IFFT_IN | RK_NL_A | RK_DIAG | RK_STORE;
 constexpr int F_DIAG = RK_DIAG;
 
 hipError_t finalize(fcn_plan_t p, double *out) {
-    return launch_finalize(p->d_inst(), p->batch, p->d_rowdiag(), p->d_zpos(), p->d_ring(), p->d_state(), out,
+    return launch_finalize(p->d_inst(), p->batch, p->d_rowdiag(), p->d_zpos(), p->d_ring(), p->d_state(0), out,
                            p->stream);
 }
 
-// Captures `steps` step bodies (column pass + middle row pass) into an executable graph.
-fcn_status ensure_graph(fcn_plan_t p, void *field, int steps) {
-    if (p->graph_exec && p->graph_steps == steps) return FCN_OK;
-    if (p->graph_exec) {
-        hipGraphExecDestroy(p->graph_exec);
-        p->graph_exec = nullptr;
+void destroy_graphs(fcn_plan_t p) {
+    for (auto &g : p->graph_exec)
+        if (g) (void)hipGraphExecDestroy(g);
+    p->graph_exec.clear();
+    p->graph_steps = 0;
+    p->graph_field = nullptr;
+}
+
+// Captures `steps` step bodies (column pass + middle row pass) of one lane (lane < 0: all
+// buckets on the bound stream) into an executable graph.
+fcn_status ensure_graph(fcn_plan_t p, void *field, int steps, int lane) {
+    const size_t slot = (size_t)(lane + 1);  // slot 0: every bucket on the bound stream
+    if (p->graph_exec.size() <= slot) p->graph_exec.resize(slot + 1, nullptr);
+    if (p->graph_exec[slot] && p->graph_steps == steps) return FCN_OK;
+    if (p->graph_exec[slot]) {
+        (void)hipGraphExecDestroy(p->graph_exec[slot]);
+        p->graph_exec[slot] = nullptr;
     }
+    const hipStream_t s = lane_stream(p, lane);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(p, e, "hipStreamBeginCapture");
     StepCtx ctx;
-    for (int s = 0; s < steps && e == hipSuccess; s++) {
-        e = col_pass(p, field, 0);
-        if (e == hipSuccess) e = row_pass(p, field, F_MIDDLE, ctx, 0);
+    for (int k = 0; k < steps && e == hipSuccess; k++) {
+        e = col_pass(p, field, 0, 0.0, nullptr, nullptr, nullptr, lane);
+        if (e == hipSuccess) e = row_pass(p, field, F_MIDDLE, ctx, 0, 0.0, nullptr, nullptr, nullptr, lane);
     }
-    hipError_t e2 = hipStreamEndCapture(p->stream, &g);
+    hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return hip_fail(p, e, "kernel launch during capture");
     }
     if (e2 != hipSuccess) return hip_fail(p, e2, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    e = hipGraphInstantiate(&p->graph_exec[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(p, e, "hipGraphInstantiate");
     p->graph_steps = steps;
     p->graph_field = field;
+    return FCN_OK;
+}
+
+// The step sequence of one lane (lane < 0: every bucket on the bound stream, with the optional
+// diagnostics records): first row pass, nsteps - 1 fused steps (graph chunks when allowed), last
+// row pass.  Does not advance the host step index.
+fcn_status run_sequence(fcn_plan_t p, void *field, int64_t nsteps, double *diag, int diag_every,
+                        const StepCtx &ctx, bool graph_ok, int lane) {
+    const bool want_diag = diag != nullptr && diag_every > 0;
+    int64_t rec = 0;
+    hipError_t e = row_pass(p, field, F_FIRST, ctx, 0, 0.0, nullptr, nullptr, nullptr, lane);
+    if (e != hipSuccess) return hip_fail(p, e, "row pass");
+    if (want_diag) {
+        e = finalize(p, diag + (rec++) * p->diag_doubles);
+        if (e != hipSuccess) return hip_fail(p, e, "finalize");
+    }
+    const hipStream_t s = lane_stream(p, lane);
+    int64_t k = 0;
+    // middle steps: k = 0 .. nsteps-2 end with a middle row pass (state A^{n0+k+1})
+    while (k < nsteps - 1) {
+        if (graph_ok) {
+            const int gs = 16;
+            if (nsteps - 1 - k >= gs) {
+                fcn_status st = ensure_graph(p, field, gs, lane);
+                if (st != FCN_OK) return st;
+                e = hipGraphLaunch(p->graph_exec[(size_t)(lane + 1)], s);
+                if (e != hipSuccess) return hip_fail(p, e, "hipGraphLaunch");
+                k += gs;
+                continue;
+            }
+        }
+        e = col_pass(p, field, 0, 0.0, nullptr, nullptr, nullptr, lane);
+        if (e == hipSuccess) e = row_pass(p, field, F_MIDDLE, ctx, 0, 0.0, nullptr, nullptr, nullptr, lane);
+        if (e != hipSuccess) return hip_fail(p, e, "step");
+        k += 1;
+        if (want_diag && k % diag_every == 0) {
+            e = finalize(p, diag + (rec++) * p->diag_doubles);
+            if (e != hipSuccess) return hip_fail(p, e, "finalize");
+        }
+    }
+    e = col_pass(p, field, 0, 0.0, nullptr, nullptr, nullptr, lane);
+    if (e == hipSuccess) e = row_pass(p, field, F_LAST, ctx, 0, 0.0, nullptr, nullptr, nullptr, lane);
+    if (e != hipSuccess) return hip_fail(p, e, "last step");
+    if (want_diag && nsteps % diag_every == 0) {
+        e = finalize(p, diag + (rec++) * p->diag_doubles);
+        if (e != hipSuccess) return hip_fail(p, e, "finalize");
+    }
     return FCN_OK;
 }
 
@@ -582,7 +679,6 @@ fcn_status run_steps(fcn_plan_t p, void *field, int64_t nsteps, double *diag, in
     if (nsteps == 0 && !diag) return FCN_OK;
     StepCtx ctx{dz_log, p->n_host, replay};
     const bool want_diag = diag != nullptr && diag_every > 0;
-    int64_t rec = 0;
     hipError_t e = hipSuccess;
     // Adaptive mode: Phi of the state before the first step seeds both slots (dz_0 from A^0).
     if (p->opt.adaptive && !p->seeded) {
@@ -595,53 +691,33 @@ fcn_status run_steps(fcn_plan_t p, void *field, int64_t nsteps, double *diag, in
         if (e == hipSuccess && want_diag) e = finalize(p, diag);
         return e == hipSuccess ? FCN_OK : hip_fail(p, e, "diagnostics");
     }
-    e = row_pass(p, field, F_FIRST, ctx, 0);
-    if (e != hipSuccess) return hip_fail(p, e, "row pass");
-    if (want_diag) {
-        e = finalize(p, diag + (rec++) * p->diag_doubles);
-        if (e != hipSuccess) return hip_fail(p, e, "finalize");
-    }
-    // graphs need a capturable (non-default) stream; they hold the field pointer
-    // and hold their kernels' arguments, so calls with a dz log (adaptive logging or replay) run eagerly
-    const bool graph_ok = p->opt.use_graph && !want_diag && p->stream != nullptr && dz_log == nullptr;
-    if (graph_ok && p->graph_exec && p->graph_field != field) {
-        hipGraphExecDestroy(p->graph_exec);
-        p->graph_exec = nullptr;
-        p->graph_steps = 0;
-    }
-    int64_t s = 0;
-    // middle steps: s = 0 .. nsteps-2 end with a middle row pass (state A^{n0+s+1})
-    while (s < nsteps - 1) {
-        int64_t chunk = 1;
-        if (graph_ok) {
-            const int gs = 16;
-            if (nsteps - 1 - s >= gs) {
-                fcn_status st = ensure_graph(p, field, gs);
-                if (st != FCN_OK) return st;
-                e = hipGraphLaunch(p->graph_exec, p->stream);
-                if (e != hipSuccess) return hip_fail(p, e, "hipGraphLaunch");
-                s += gs;
-                continue;
-            }
+    // Lanes run concurrently only without diagnostics records or a dz log (both need every
+    // instance at the same step between launches) and outside allocation-free calls.
+    const bool lanes = p->nlanes > 1 && !p->serial && !want_diag && dz_log == nullptr &&
+                       (int)p->lane_streams.size() == p->nlanes;
+    // graphs need a capturable (non-default) stream; they hold the field pointer and their
+    // kernels' arguments, so calls with a dz log (adaptive logging or replay) run eagerly
+    const bool graph_ok = p->opt.use_graph && !p->serial && !want_diag && dz_log == nullptr &&
+                          (lanes || p->stream != nullptr);
+    if (graph_ok && p->graph_field != nullptr && p->graph_field != field) destroy_graphs(p);
+    fcn_status st = FCN_OK;
+    if (!lanes) {
+        st = run_sequence(p, field, nsteps, diag, diag_every, ctx, graph_ok, -1);
+    } else {
+        e = hipEventRecord(p->fork_event, p->stream);
+        for (int l = 0; l < p->nlanes && e == hipSuccess; l++) e = hipStreamWaitEvent(p->lane_streams[l], p->fork_event, 0);
+        if (e != hipSuccess) return hip_fail(p, e, "fork to the lane streams");
+        for (int l = 0; l < p->nlanes && st == FCN_OK; l++)
+            st = run_sequence(p, field, nsteps, nullptr, 0, ctx, graph_ok, l);
+        // join even after a failed launch, so the bound stream never runs ahead of the lanes
+        for (int l = 0; l < p->nlanes && e == hipSuccess; l++) {
+            e = hipEventRecord(p->lane_events[l], p->lane_streams[l]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->lane_events[l], 0);
         }
-        e = col_pass(p, field, 0);
-        if (e == hipSuccess) e = row_pass(p, field, F_MIDDLE, ctx, 0);
-        if (e != hipSuccess) return hip_fail(p, e, "step");
-        s += chunk;
-        if (want_diag && s % diag_every == 0) {
-            e = finalize(p, diag + (rec++) * p->diag_doubles);
-            if (e != hipSuccess) return hip_fail(p, e, "finalize");
-        }
+        if (st == FCN_OK && e != hipSuccess) st = hip_fail(p, e, "join of the lane streams");
     }
-    e = col_pass(p, field, 0);
-    if (e == hipSuccess) e = row_pass(p, field, F_LAST, ctx, 0);
-    if (e != hipSuccess) return hip_fail(p, e, "last step");
-    p->n_host += nsteps;
-    if (want_diag && nsteps % diag_every == 0) {
-        e = finalize(p, diag + (rec++) * p->diag_doubles);
-        if (e != hipSuccess) return hip_fail(p, e, "finalize");
-    }
-    return FCN_OK;
+    if (st == FCN_OK) p->n_host += nsteps;
+    return st;
 }
 
 }  // namespace
@@ -720,7 +796,7 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
         delete p;
         return FCN_E_ARG;
     }
-    if (p->opt.reserved != 0) {
+    if (p->opt.lanes < 0 || p->opt.lanes > 8) {
         delete p;
         return FCN_E_ARG;
     }
@@ -788,17 +864,26 @@ fcn_status fcn_plan_bind(fcn_plan_t p, void *workspace_dev, size_t workspace_byt
     if (((uintptr_t)workspace_dev & 255) != 0) return fail(p, FCN_E_ARG, "workspace must be 256-byte aligned");
     if (workspace_bytes < p->ws_bytes)
         return fail(p, FCN_E_SIZE, "workspace has %zu bytes, plan needs %zu", workspace_bytes, p->ws_bytes);
-    if (p->graph_exec) {
-        hipGraphExecDestroy(p->graph_exec);
-        p->graph_exec = nullptr;
-        p->graph_steps = 0;
-    }
+    destroy_graphs(p);
     p->ws = static_cast<unsigned char *>(workspace_dev);
     p->stream = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->ws, p->image.data(), p->const_bytes, hipMemcpyHostToDevice, p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "upload plan tables");
-    e = launch_init_state(p->d_state(), p->d_slots(), p->d_ring(), p->d_zpos(), p->batch, 0, p->stream);
+    e = launch_init_state(p->d_state(0), p->nlanes, p->d_slots(), p->d_ring(), p->d_zpos(), p->batch, 0, p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "init state");
+    // helper streams of the lanes (default priority; kept across binds, released by destroy)
+    if (p->nlanes > 1 && p->lane_streams.empty()) {
+        e = hipEventCreateWithFlags(&p->fork_event, hipEventDisableTiming);
+        for (int l = 0; l < p->nlanes && e == hipSuccess; l++) {
+            hipStream_t ls = nullptr;
+            hipEvent_t le = nullptr;
+            e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking);
+            if (e == hipSuccess) p->lane_streams.push_back(ls);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&le, hipEventDisableTiming);
+            if (e == hipSuccess) p->lane_events.push_back(le);
+        }
+        if (e != hipSuccess) return hip_fail(p, e, "lane streams");
+    }
     // the host image must stay alive until the copy has run
     e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "hipStreamSynchronize");
@@ -856,11 +941,16 @@ fcn_status fcn_sync(fcn_plan_t p) {
     if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "hipStreamSynchronize");
-    int32_t flags[2] = {0, 0};  // DevState::nonfinite, DevState::unstable (adjacent)
-    e = hipMemcpy(flags, &p->d_state()->nonfinite, sizeof flags, hipMemcpyDeviceToHost);
+    std::vector<DevState> states((size_t)p->nlanes);
+    e = hipMemcpy(states.data(), p->d_state(0), sizeof(DevState) * states.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(p, e, "read flags");
+    int32_t flags[2] = {0, 0};  // any lane's nonfinite, unstable
+    for (const auto &x : states) {
+        flags[0] |= x.nonfinite;
+        flags[1] |= x.unstable;
+    }
     if (flags[0] || flags[1]) {
-        e = launch_clear_flag(p->d_state(), p->stream);
+        e = launch_clear_flag(p->d_state(0), p->nlanes, p->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
         if (flags[1])
             return fail(p, FCN_E_UNSTABLE,
@@ -891,7 +981,8 @@ fcn_status fcn_step_scratch(fcn_plan_t p, void *field_dev, int64_t nsteps, void 
     p->ws = scr;
     p->stream = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->ws, p->image.data(), p->const_bytes, hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = launch_init_state(p->d_state(), p->d_slots(), p->d_ring(), p->d_zpos(), p->batch, 0, p->stream);
+    if (e == hipSuccess)
+        e = launch_init_state(p->d_state(0), p->nlanes, p->d_slots(), p->d_ring(), p->d_zpos(), p->batch, 0, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // the host image is read by the copy
     if (e != hipSuccess) {
         st = hip_fail(p, e, "upload plan tables to the static scratch");
@@ -900,7 +991,9 @@ fcn_status fcn_step_scratch(fcn_plan_t p, void *field_dev, int64_t nsteps, void 
         p->n_host = 0;
         p->seeded = false;
         p->opt.use_graph = 0;  // a graph would hold this call's addresses
+        p->serial = true;      // every lane on the given stream: no helper streams, no events
         st = run_steps(p, field_dev, nsteps, nullptr, 0, nullptr, 0);
+        p->serial = false;
     }
     p->ws = ws0;
     p->stream = stream0;
@@ -1006,16 +1099,16 @@ fcn_status fcn_step_timed_launches(fcn_plan_t p, void *field_dev, int64_t nsteps
         int64_t pts = 0;
         if (l < nrow) {
             const auto &b = p->row_buckets[l];
-            for (const auto &d : p->dinst)
-                if (d.nt == b.nt) pts += (int64_t)d.nr * d.nt;
+            for (int i = 0; i < p->batch; i++)
+                if (p->dinst[i].nt == b.nt && p->lane_of[i] == b.lane) pts += (int64_t)p->dinst[i].nr * p->dinst[i].nt;
             launch_info[5 * l] = 0;
             launch_info[5 * l + 1] = b.nt;
             launch_info[5 * l + 3] = row_elems_for(b.nt, row_fp64_arith(p->precision));
             launch_info[5 * l + 4] = row_rows_per_group(b.nt, (int)launch_info[5 * l + 3]);
         } else {
             const auto &b = p->col_buckets[l - nrow];
-            for (const auto &d : p->dinst)
-                if (d.nr == b.nr) pts += (int64_t)d.nr * d.nt;
+            for (int i = 0; i < p->batch; i++)
+                if (p->dinst[i].nr == b.nr && p->lane_of[i] == b.lane) pts += (int64_t)p->dinst[i].nr * p->dinst[i].nt;
             launch_info[5 * l] = 1;
             launch_info[5 * l + 1] = b.nr;
             launch_info[5 * l + 3] = b.w;
@@ -1030,7 +1123,10 @@ const char *fcn_last_error(fcn_plan_t p) { return p ? p->err.c_str() : "NULL pla
 
 fcn_status fcn_plan_destroy(fcn_plan_t p) {
     if (!p) return FCN_E_ARG;
-    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+    destroy_graphs(p);
+    for (auto ls : p->lane_streams) (void)hipStreamDestroy(ls);
+    for (auto le : p->lane_events) (void)hipEventDestroy(le);
+    if (p->fork_event) (void)hipEventDestroy(p->fork_event);
     delete p;
     return FCN_OK;
 }

@@ -76,7 +76,7 @@ class Options(ctypes.Structure):
         ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32),
         ("max_phase", ctypes.c_double), ("dz_min", ctypes.c_double), ("dz_max", ctypes.c_double),
         ("use_graph", ctypes.c_int32), ("col_tile", ctypes.c_int32), ("col_rows", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+        ("lanes", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
     ]
 
 
@@ -160,7 +160,7 @@ class Plan:
 
     def __init__(self, instances, precision: str = "fp64", adaptive: bool = False, max_phase: float = 0.05,
                  dz_min: float = 1e-6, dz_max: float = 1e-2, use_graph: bool = False, col_tile: int = 0,
-                 col_rows: int = 0, device: int = 0, stream=None, tune_cache: str | None = None):
+                 col_rows: int = 0, device: int = 0, stream=None, tune_cache: str | None = None, lanes: int = 0):
         import torch
 
         if not torch.cuda.is_available():
@@ -179,7 +179,7 @@ class Plan:
         arr = (Instance * self.batch)(*[make_instance(i) for i in self.instances])
         opt = Options(precision=PRECISIONS[precision], adaptive=int(adaptive),
                       max_phase=max_phase, dz_min=dz_min, dz_max=dz_max, use_graph=int(use_graph),
-                      col_tile=col_tile, col_rows=col_rows, reserved=0,
+                      col_tile=col_tile, col_rows=col_rows, lanes=lanes,
                       tune_cache=tune_cache.encode() if tune_cache else None)
         self._h = ctypes.c_void_p()
         rc = self.lib.fcn_plan_create(arr, self.batch, ctypes.byref(opt), ctypes.byref(self._h))

@@ -43,7 +43,7 @@ def _create(lib, insts, precision, cache):
     from paper_1507_05988_amd import fcn
     arr = (fcn.Instance * len(insts))(*[fcn.make_instance(i) for i in insts])
     o = fcn.Options(precision=fcn.PRECISIONS[precision], adaptive=0, max_phase=0.05, dz_min=1e-6, dz_max=1e-2,
-                    use_graph=0, col_tile=0, col_rows=0, reserved=0, tune_cache=cache.encode() if cache else None)
+                    use_graph=0, col_tile=0, col_rows=0, lanes=0, tune_cache=cache.encode() if cache else None)
     h = ctypes.c_void_p()
     rc = lib.fcn_plan_create(arr, len(insts), ctypes.byref(o), ctypes.byref(h))
     return rc, h

@@ -434,6 +434,53 @@ def test_graph_plans_with_dz_log_match_eager():
         assert e < 1e-5
 
 
+def test_lanes_give_the_bits_of_one_lane():
+    """Instances split into 3 concurrent lanes (own streams, own step counters) give the same
+    bits as one lane: eager and graph-replayed steps, adaptive dz, diagnostics records (which
+    run the lanes in turn on the bound stream), and a non-finite intensity in an instance of
+    another lane than the first is still reported."""
+    import torch
+    insts = wl.config_batch(count=7, seed=21)
+    for i in insts:
+        i["nr"] = min(i["nr"], 256)
+    stream = torch.cuda.Stream()
+    fields = [wl.gaussian_field(i, np.complex64) for i in insts]
+    with torch.cuda.stream(stream):
+        outs = {}
+        for lanes, graph in ((1, False), (3, False), (3, True), (1, True)):
+            p = _plan(insts, "fp32_cn64", lanes=lanes, use_graph=graph, stream=stream)
+            f = p.pack(fields)
+            p.step(f, 37)
+            p.step(f, 20)
+            p.sync()
+            outs[(lanes, graph)] = p.unpack(f)
+        for key, got in outs.items():
+            for a, b in zip(outs[(1, False)], got):
+                assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), key
+        # adaptive dz without a log (lanes concurrent), then records (lanes in turn)
+        res = {}
+        for lanes in (1, 3):
+            p = _plan(insts, "fp64", lanes=lanes, adaptive=True, stream=stream)
+            f = p.pack([x.astype(np.complex128) for x in fields])
+            p.step(f, 9)
+            d = p.propagate(f, 6, diag_every=3)
+            p.sync()
+            res[lanes] = (p.unpack(f), d.cpu().numpy())
+        for a, b in zip(res[1][0], res[3][0]):
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+        assert np.array_equal(res[1][1], res[3][1])
+        # flags of every lane reach fcn_sync
+        p = _plan(insts, "fp64", lanes=3, stream=stream)
+        bad = [x.astype(np.complex128) for x in fields]
+        bad[-1][2, 7] = np.nan
+        f = p.pack(bad)
+        p.step(f, 2)
+        with pytest.raises(fcn.FcnError) as ei:
+            p.sync()
+        assert ei.value.code == fcn.FCN_E_NONFINITE
+        p.sync()
+
+
 @pytest.mark.parametrize("precision,nr,ipk", [("fp64", 40, 5e17), ("fp64", 64, 6e17), ("fp32_cn64", 64, 6e17)])
 def test_step_splitting_is_exact(precision, nr, ipk):
     """step(n) then step(m) equals step(n+m) bitwise (state carried in the workspace; the fused

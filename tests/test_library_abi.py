@@ -37,7 +37,7 @@ def _create(lib, insts, **opt):
     o = fcn.Options(precision=opt.get("precision", 0), adaptive=opt.get("adaptive", 0),
                     max_phase=opt.get("max_phase", 0.05), dz_min=opt.get("dz_min", 1e-6),
                     dz_max=opt.get("dz_max", 1e-2), use_graph=0, col_tile=opt.get("col_tile", 0),
-                    col_rows=opt.get("col_rows", 0), reserved=0)
+                    col_rows=opt.get("col_rows", 0), lanes=0)
     h = ctypes.c_void_p()
     rc = lib.fcn_plan_create(arr, len(insts), ctypes.byref(o), ctypes.byref(h))
     return rc, h

@@ -60,7 +60,9 @@ enum {
     FCN_KERR = 4,        /* i (k0/n0) sum_j n_2j |A|^2j of Eq. nonlinearpart */
     FCN_PLASMA = 8,      /* -(i k0/2) omega_pe^2/omega0^2 = -(i k0/2) rho/rho_c */
     FCN_MPA = 16,        /* -(beta_K/2) |A|^(2K-2), beta_K = K hbar omega0 sigma_K rho_at */
-    FCN_COLL = 32        /* -(sigma_c/2) rho, collisional absorption (not in the paper) */
+    FCN_COLL = 32,       /* -(sigma_c/2) rho, collisional absorption (not in the paper) */
+    FCN_AVALANCHE = 64   /* avalanche ionisation: (sigma_c / U_i) |A|^2 rho added to the density
+                            rate of Eq. ionization (not in the paper) */
 };
 
 /* Precision modes.  FCN_FP32_STORAGE keeps the field in FP32 (the HBM traffic of FCN_FP32)
@@ -87,6 +89,7 @@ typedef struct {
     double sigma_K;          /* [s^-1 (m^2/W)^K] */
     double rho_at;           /* neutral density [m^-3] */
     double sigma_c;          /* collisional cross-section [m^2] */
+    double U_i;              /* ionisation potential [J] of the avalanche rate (> 0 with FCN_AVALANCHE) */
     double dz;               /* step length [m] (fixed mode), ignored when adaptive */
     uint32_t terms;          /* OR of the FCN_* term switches */
 } fcn_instance;

@@ -38,12 +38,13 @@ struct DevInst {
     double phi_kerr;        // 1 if the Kerr rate enters Phi
     double phi_plasma;      // k0/(2 rho_c) if the plasma rate enters Phi, else 0
     double need_ik1;        // 1 if I^(K-1) is used (MPA on, or the density scan)
+    double c_aval;          // sigma_c / U_i, the avalanche rate per intensity (0 when off)
     // FP32 nonlinear step on the scaled intensity u = I / I_ref, I_ref = (sigma_K dtau)^(-1/K)
     // when the density is on (so sigma_K I^K dtau = u^K), else 1/|ck1| (or 1):
     float f_inv_iref;       // 1 / I_ref
     float fk1, fk2, fk3, fk4;  // ck_j I_ref^j
     float f_mpa;            // c_mpa I_ref^(K-1)
-    float f_ghalf;          // unused padding
+    float f_aval;           // c_aval I_ref dtau: the avalanche rate in units of the scaled intensity
     float f_pad;
 };
 
@@ -83,6 +84,7 @@ enum : int {
     RK_TW_PAIR = 256,   // FP32 transforms with twiddles carried as hi + lo pairs
     RK_NOABS = 512,     // no instance of the launch has a density or absorption term (MPA,
                         // collisions): the nonlinear step is the Kerr phase rotation alone
+    RK_AVAL = 1024,     // with RK_SCAN: some instance has the avalanche rate in its density equation
 };
 
 // Step-length source of a row kernel.

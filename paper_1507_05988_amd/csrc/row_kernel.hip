@@ -301,6 +301,11 @@ struct NlPoint<double> {
     static __device__ __forceinline__ double dt_g_of(double Imid, const DevInst &in) {
         return in.dtau * in.sigma_K * ipow(Imid, in.K);
     }
+    // avalanche rate times dtau, dtau (sigma_c / U_i) I
+    __device__ __forceinline__ double dt_a(const DevInst &in) const { return in.dtau * in.c_aval * I; }
+    static __device__ __forceinline__ double dt_a_of(double Imid, const DevInst &in) {
+        return in.dtau * in.c_aval * Imid;
+    }
     __device__ __forceinline__ double mid_arg(const NlPoint &o) const { return 0.5 * (I + o.I); }
     __device__ __forceinline__ double kerr(const DevInst &in) const {
         return I * (in.ck1 + I * (in.ck2 + I * (in.ck3 + I * in.ck4)));
@@ -327,6 +332,8 @@ struct NlPoint<float> {
     __device__ __forceinline__ double intensity() const { return (double)ii; }
     __device__ __forceinline__ float dt_g(const DevInst &) const { return uk1 * u; }
     static __device__ __forceinline__ float dt_g_of(float umid, const DevInst &in) { return ipowf_(umid, in.K); }
+    __device__ __forceinline__ float dt_a(const DevInst &in) const { return in.f_aval * u; }
+    static __device__ __forceinline__ float dt_a_of(float umid, const DevInst &in) { return in.f_aval * umid; }
     __device__ __forceinline__ float mid_arg(const NlPoint &o) const { return 0.5f * (u + o.u); }
     __device__ __forceinline__ float kerr_f(const DevInst &in) const {
         return u * (in.fk1 + u * (in.fk2 + u * (in.fk3 + u * in.fk4)));
@@ -360,8 +367,16 @@ struct NlPoint<float> {
 // constant rate) sets *unstable: the density then leaves [0, rho_at] and runs away.
 // NOABS (launches whose instances have neither a density nor an absorption term, scan false):
 // N = i Kerr rate, a pure phase rotation.
+// AVAL (scan true, some instance with the avalanche rate): the density equation
+// d rho/dt = g (rho_at - rho) + a rho, g = sigma_K I^K, a = (sigma_c/U_i) I, is linear with
+// coefficients d = a - g and source g rho_at; one RK4 step is rho -> (1 - P) rho + Q rho_at with
+// P = -(D0 + 2 Dh v2 + 2 Dh v3 + D1 v4)/6, v2 = 1 + D0/2, v3 = 1 + Dh v2/2, v4 = 1 + Dh v3, and
+// Q = (G0 + 2 w2 + 2 w3 + w4)/6, w2 = Gh + Dh G0/2, w3 = Gh + Dh w2/2, w4 = G1 + D1 w3, in units of
+// dtau (D = (a - g) dtau, G = g dtau at the interval's start, middle and end); without the
+// avalanche P = Q = S.  An RK4 factor 1 - P < 0 or Q < 0 (the exact ones are positive) sets
+// *unstable.
 // Must be called by every thread of the workgroup (the scan holds barriers when T > 64).
-template <typename R, int T, int E, bool NOABS>
+template <typename R, int T, int E, bool NOABS, bool AVAL>
 __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevInst &in, R h, bool apply,
                                             bool diag, bool scan, bool upd_next, DiagAcc &acc, int tr,
                                             RowScratch &sh, int32_t *unstable) {
@@ -379,7 +394,8 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevI
         pn.load(nx, in, k1);
         const bool need_rho = in.need_rho != 0.0;
         const double ra = in.rho_at;
-        S_t S[E];
+        S_t S[E];             // P (= Q without the avalanche)
+        S_t Qv[AVAL ? E : 1];  // Q with the avalanche
         double ca = 1.0, cb = 0.0;
         S_t a0 = pt[0].dt_g(in);
         bool bad = false;
@@ -388,19 +404,40 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevI
             const NlPoint<R> &p1 = (k + 1 < E) ? pt[k + 1] : pn;
             const S_t a1 = p1.dt_g(in);
             const S_t ah = NlPoint<R>::dt_g_of(pt[k].mid_arg(p1), in);
-            // one classical RK4 step of d rho/dt = g(t) (rho_at - rho), in units of dt g:
-            // rho' = rho + S (rho_at - rho)
             const S_t one = S_t(1), half = S_t(0.5);
-            const S_t u2 = one - half * a0;
-            const S_t u3 = one - half * ah * u2;
-            const S_t u4 = one - ah * u3;
-            const S_t sv = (a0 + S_t(2) * ah * u2 + S_t(2) * ah * u3 + a1 * u4) * S_t(1.0 / 6.0);
-            S[k] = need_rho ? sv : S_t(0);
             // the row's last interval (last thread, last point) wraps to t_min and is never used
-            if (!(S[k] >= S_t(0) && S[k] <= S_t(1)) && (k + 1 < E || tr + 1 < T)) bad = true;
-            const double sd = (double)S[k];
-            cb = (1.0 - sd) * cb + sd * ra;  // compose after the chunk's earlier steps
-            ca = (1.0 - sd) * ca;
+            const bool used = k + 1 < E || tr + 1 < T;
+            if constexpr (AVAL) {
+                const S_t d0 = pt[k].dt_a(in) - a0;
+                const S_t dh = NlPoint<R>::dt_a_of(pt[k].mid_arg(p1), in) - ah;
+                const S_t d1 = p1.dt_a(in) - a1;
+                const S_t v2 = one + half * d0;
+                const S_t v3 = one + half * dh * v2;
+                const S_t v4 = one + dh * v3;
+                const S_t pv = -(d0 + S_t(2) * dh * v2 + S_t(2) * dh * v3 + d1 * v4) * S_t(1.0 / 6.0);
+                const S_t w2 = ah + half * dh * a0;
+                const S_t w3 = ah + half * dh * w2;
+                const S_t w4 = a1 + d1 * w3;
+                const S_t qv = (a0 + S_t(2) * w2 + S_t(2) * w3 + w4) * S_t(1.0 / 6.0);
+                S[k] = need_rho ? pv : S_t(0);
+                Qv[k] = need_rho ? qv : S_t(0);
+                if (!(S[k] <= S_t(1) && Qv[k] >= S_t(0)) && used) bad = true;
+                const double pd = (double)S[k], qd = (double)Qv[k];
+                cb = (1.0 - pd) * cb + qd * ra;
+                ca = (1.0 - pd) * ca;
+            } else {
+                // one classical RK4 step of d rho/dt = g(t) (rho_at - rho), in units of dt g:
+                // rho' = rho + S (rho_at - rho)
+                const S_t u2 = one - half * a0;
+                const S_t u3 = one - half * ah * u2;
+                const S_t u4 = one - ah * u3;
+                const S_t sv = (a0 + S_t(2) * ah * u2 + S_t(2) * ah * u3 + a1 * u4) * S_t(1.0 / 6.0);
+                S[k] = need_rho ? sv : S_t(0);
+                if (!(S[k] >= S_t(0) && S[k] <= S_t(1)) && used) bad = true;
+                const double sd = (double)S[k];
+                cb = (1.0 - sd) * cb + sd * ra;  // compose after the chunk's earlier steps
+                ca = (1.0 - sd) * ca;
+            }
             a0 = a1;
         }
         if (bad) atomicOr(unstable, 1);
@@ -409,7 +446,7 @@ __device__ __forceinline__ void nl_sub_step(c2<R> (&c)[E], c2<R> &nx, const DevI
         for (int k = 0; k < E; k++) {
             rho[k] = r;
             const double sd = (double)S[k];
-            r = (1.0 - sd) * r + sd * ra;
+            r = (1.0 - sd) * r + (AVAL ? (double)Qv[AVAL ? k : 0] : sd) * ra;
         }
     } else {
 #pragma unroll
@@ -550,6 +587,8 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
         // term applies the nonlinear step pointwise on the strided registers instead
         constexpr bool scan = (FLAGS & RK_SCAN) != 0;
         constexpr bool NOABS = (FLAGS & RK_NOABS) != 0;
+        constexpr bool AVAL = (FLAGS & RK_AVAL) != 0;
+        static_assert(!AVAL || scan, "the avalanche rate is part of the density scan");
         static_assert(!(scan && NOABS), "a launch without absorption or density has no scan");
         const R ha = R(0.5 * dz_a), hb = R(0.5 * dz_b);
         constexpr bool DO_A = (FLAGS & RK_NL_A) != 0;
@@ -565,9 +604,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
             for (int k = 0; k < E; k++) c[k] = row_lds[lpad(tr * E + k)];
             c2<R> nx = row_lds[lpad(tr < T - 1 ? tr * E + E : 0)];
             int32_t *unst = &a.state->unstable;
-            if constexpr (DO_A) nl_sub_step<R, T, E, false>(c, nx, in, ha, true, false, true, true, acc, tr, sh, unst);
+            if constexpr (DO_A) nl_sub_step<R, T, E, false, AVAL>(c, nx, in, ha, true, false, true, true, acc, tr, sh, unst);
             if constexpr (DO_B || DO_D)
-                nl_sub_step<R, T, E, false>(c, nx, in, hb, DO_B, DO_D, true, false, acc, tr, sh, unst);
+                nl_sub_step<R, T, E, false, AVAL>(c, nx, in, hb, DO_B, DO_D, true, false, acc, tr, sh, unst);
             if constexpr ((FLAGS & RK_STORE) != 0) {
                 __syncthreads();
 #pragma unroll
@@ -579,9 +618,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
         } else {
             c2<R> unused = czero<R>();
             int32_t *unst = &a.state->unstable;
-            if constexpr (DO_A) nl_sub_step<R, T, E, NOABS>(v, unused, in, ha, true, false, false, false, acc, tr, sh, unst);
+            if constexpr (DO_A) nl_sub_step<R, T, E, NOABS, false>(v, unused, in, ha, true, false, false, false, acc, tr, sh, unst);
             if constexpr (DO_B || DO_D)
-                nl_sub_step<R, T, E, NOABS>(v, unused, in, hb, DO_B, DO_D, false, false, acc, tr, sh, unst);
+                nl_sub_step<R, T, E, NOABS, false>(v, unused, in, hb, DO_B, DO_D, false, false, acc, tr, sh, unst);
         }
         if constexpr (DO_D) {
             acc = row_reduce<T>(acc, tr, sh);
@@ -676,6 +715,16 @@ static hipError_t launch_row_p(int nt, int flags, const RowArgs &a, int grid, hi
         case RK_LAST | RK_SCAN: return launch_row_nt<R, ST, (RK_LAST | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
         case RK_DIAG_ONLY | RK_SCAN: return launch_row_nt<R, ST, (RK_DIAG_ONLY | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
         case RK_T_NL | RK_SCAN: return launch_row_nt<R, ST, (RK_T_NL | RK_SCAN) | X>(nt, a, grid, s, e0, e1);
+        case RK_FIRST | RK_SCAN | RK_AVAL:
+            return launch_row_nt<R, ST, (RK_FIRST | RK_SCAN | RK_AVAL) | X>(nt, a, grid, s, e0, e1);
+        case RK_MIDDLE | RK_SCAN | RK_AVAL:
+            return launch_row_nt<R, ST, (RK_MIDDLE | RK_SCAN | RK_AVAL) | X>(nt, a, grid, s, e0, e1);
+        case RK_LAST | RK_SCAN | RK_AVAL:
+            return launch_row_nt<R, ST, (RK_LAST | RK_SCAN | RK_AVAL) | X>(nt, a, grid, s, e0, e1);
+        case RK_DIAG_ONLY | RK_SCAN | RK_AVAL:
+            return launch_row_nt<R, ST, (RK_DIAG_ONLY | RK_SCAN | RK_AVAL) | X>(nt, a, grid, s, e0, e1);
+        case RK_T_NL | RK_SCAN | RK_AVAL:
+            return launch_row_nt<R, ST, (RK_T_NL | RK_SCAN | RK_AVAL) | X>(nt, a, grid, s, e0, e1);
         case RK_FIRST | RK_NOABS: return launch_row_nt<R, ST, (RK_FIRST | RK_NOABS) | X>(nt, a, grid, s, e0, e1);
         case RK_MIDDLE | RK_NOABS: return launch_row_nt<R, ST, (RK_MIDDLE | RK_NOABS) | X>(nt, a, grid, s, e0, e1);
         case RK_LAST | RK_NOABS: return launch_row_nt<R, ST, (RK_LAST | RK_NOABS) | X>(nt, a, grid, s, e0, e1);

@@ -45,8 +45,9 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct RowBucket {
     int lane;
     int nt;
-    int scan;  // RK_SCAN when an instance of the bucket has a density term, RK_NOABS when none
-               // has a density or absorption term, else 0
+    int scan;  // RK_SCAN when an instance of the bucket has a density term (| RK_AVAL when one
+               // also has the avalanche rate), RK_NOABS when none has a density or absorption
+               // term, else 0
     int item_off, nitems;
     int grid;
 };
@@ -148,7 +149,9 @@ const char *check_instance(const fcn_instance &in) {
         return "non-finite dispersion or Kerr coefficient";
     if (in.K < 1 || in.K > 16) return "K must be in [1, 16]";
     if (!(in.sigma_K >= 0.0) || !(in.rho_at >= 0.0) || !(in.sigma_c >= 0.0)) return "negative density coefficient";
-    if ((in.terms & ~63u) != 0) return "unknown term bit";
+    if ((in.terms & ~127u) != 0) return "unknown term bit";
+    if ((in.terms & FCN_AVALANCHE) && !(in.U_i > 0.0 && std::isfinite(in.U_i)))
+        return "the avalanche term needs a positive ionisation potential U_i";
     if (!(in.dz >= 0.0) || !std::isfinite(in.dz)) return "dz must be finite and non-negative";
     return nullptr;
 }
@@ -358,6 +361,7 @@ fcn_status build_plan(fcn_plan_t p) {
         d.phi_kerr = kerr ? 1.0 : 0.0;
         d.phi_plasma = (in.terms & FCN_PLASMA) ? k0 / (2.0 * rho_c) : 0.0;
         d.need_ik1 = (d.need_rho != 0.0 || d.c_mpa != 0.0) ? 1.0 : 0.0;
+        d.c_aval = (in.terms & FCN_AVALANCHE) ? in.sigma_c / in.U_i : 0.0;
         double iref = 1.0;
         if (d.need_rho != 0.0)
             iref = std::pow(in.sigma_K * d.dtau, -1.0 / (double)in.K);
@@ -371,6 +375,7 @@ fcn_status build_plan(fcn_plan_t p) {
         d.fk3 = (float)(d.ck3 * iref * iref * iref);
         d.fk4 = (float)(d.ck4 * iref * iref * iref * iref);
         d.f_mpa = (float)(d.c_mpa * std::pow(iref, (double)(in.K - 1)));
+        d.f_aval = (float)(d.c_aval * iref * d.dtau);
         p->dinst[i] = d;
         off += (size_t)in.nr * in.nt;
         row += in.nr;
@@ -412,9 +417,10 @@ fcn_status build_plan(fcn_plan_t p) {
         // if no instance has an absorption term either
         b.scan = RK_NOABS;
         for (int i : kv.second) {
-            if (p->dinst[i].need_rho != 0.0) b.scan = RK_SCAN;
-            if (p->dinst[i].c_mpa != 0.0 || p->dinst[i].c_coll != 0.0)
-                if (b.scan != RK_SCAN) b.scan = 0;
+            if (p->dinst[i].need_rho != 0.0) b.scan |= RK_SCAN;
+            if (p->dinst[i].need_rho != 0.0 && p->dinst[i].c_aval != 0.0) b.scan |= RK_AVAL;
+            if (p->dinst[i].c_mpa != 0.0 || p->dinst[i].c_coll != 0.0 || p->dinst[i].need_rho != 0.0)
+                b.scan &= ~RK_NOABS;
         }
         const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)));
         b.grid = (b.nitems + rpw - 1) / rpw;

@@ -50,7 +50,7 @@ class Instance(ctypes.Structure):
         ("n2", ctypes.c_double), ("n4", ctypes.c_double), ("n6", ctypes.c_double), ("n8", ctypes.c_double),
         ("K", ctypes.c_int32),
         ("sigma_K", ctypes.c_double), ("rho_at", ctypes.c_double), ("sigma_c", ctypes.c_double),
-        ("dz", ctypes.c_double),
+        ("U_i", ctypes.c_double), ("dz", ctypes.c_double),
         ("terms", ctypes.c_uint32),
     ]
 
@@ -143,7 +143,7 @@ def load_library(path: str = LIB_PATH):
 def make_instance(inst: dict) -> Instance:
     c = Instance()
     for name, _ in Instance._fields_:
-        val = inst[name]
+        val = inst.get(name, 0.0) if name == "U_i" else inst[name]
         setattr(c, name, int(val) if name in ("nr", "nt", "K", "terms") else float(val))
     return c
 

@@ -9,7 +9,7 @@ no nonlinear operator) and it imports nothing from the HIP binding or the oracle
 Units are SI throughout.  A workload is a list of instance dicts whose keys match
 the ``fcn_instance`` struct of ``include/fcn.h``:
 ``nr, nt, r_max, t_min, t_max, lambda0, n0, k2, n2, n4, n6, n8, K, sigma_K, rho_at,
-sigma_c, dz, terms`` plus the pulse keys ``w0, tau, P, I0, chirp`` that only the
+sigma_c, U_i, dz, terms`` plus the pulse keys ``w0, tau, P, I0, chirp`` that only the
 initial field uses.
 """
 from __future__ import annotations
@@ -25,6 +25,7 @@ KERR = 4         # sum_j n_{2j} |A|^{2j} of Eq. nonlinearpart
 PLASMA = 8       # plasma defocusing term of Eq. nonlinearpart
 MPA = 16         # multiphoton absorption term of Eq. nonlinearpart
 COLL = 32        # collisional absorption, -(sigma_c/2) rho (not in the paper)
+AVALANCHE = 64   # avalanche ionisation, (sigma_c / U_i) I rho in the density rate (not in the paper)
 ALL_TERMS = DIFFRACTION | GVD | KERR | PLASMA | MPA | COLL
 KERR_ONLY = DIFFRACTION | GVD | KERR
 
@@ -36,6 +37,8 @@ K2_AIR = 2e-29            # k'' [s^2/m] = 0.2 fs^2/cm (Sec. 2, after Eq. nlse)
 # sigma_c = k0 w0 tau_c / (n0 rho_c (1 + w0^2 tau_c^2)); evaluated once with CODATA
 # constants and stored as a plain input coefficient.
 SIGMA_C_800NM = 5.471072962824351e-24
+# Ionisation potential of O2, 12.06 eV, for the avalanche rate (sigma_c / U_i) I rho.
+U_I_O2 = 12.06 * 1.602176634e-19
 
 
 def critical_power(lambda0: float, n0: float, n2: float) -> float:
@@ -88,12 +91,12 @@ def _pulse(inst: dict, w0: float, tau: float, p_over_pcr: float) -> dict:
 
 
 def _base(nr, nt, w0, tau, *, r_max=None, t_half=None, n2=0.0, n4=0.0, k2=K2_AIR,
-          K=8, sigma_K=0.0, rho_at=0.0, sigma_c=0.0, dz=0.0, terms=KERR_ONLY):
+          K=8, sigma_K=0.0, rho_at=0.0, sigma_c=0.0, U_i=0.0, dz=0.0, terms=KERR_ONLY):
     r_max = 4.0 * w0 if r_max is None else r_max
     t_half = 4.0 * tau if t_half is None else t_half
     return dict(nr=nr, nt=nt, r_max=r_max, t_min=-t_half, t_max=t_half, lambda0=LAMBDA0, n0=1.0,
                 k2=k2, n2=n2, n4=n4, n6=0.0, n8=0.0, K=K, sigma_K=sigma_K, rho_at=rho_at,
-                sigma_c=sigma_c, dz=dz, terms=terms)
+                sigma_c=sigma_c, U_i=U_i, dz=dz, terms=terms)
 
 
 # Full-model coefficient set: Kerr n2 and the alternating-sign n4, 8-photon ionisation
@@ -191,6 +194,16 @@ def config_higher_kerr(nr=256, nt=1024, chirp=-1.5) -> dict:
     inst = config_full(nr=nr, nt=nt)
     inst.update(n6=4e-60, n8=-2e-77, chirp=chirp)
     inst["I0"] = 5e17
+    return inst
+
+
+def config_avalanche(nr=256, nt=1024, peak=7e17) -> dict:
+    """Full-model pulse with avalanche ionisation added to the density rate: the full-model grid
+    and coefficients, U_i of O2, scaled to `peak` W/m^2 (where the avalanche rate sigma_c I / U_i,
+    about 2e12 1/s, turns a few percent of the pulse's density over its length)."""
+    inst = config_full(nr=nr, nt=nt)
+    inst.update(U_i=U_I_O2, terms=ALL_TERMS | AVALANCHE)
+    inst["I0"] = peak
     return inst
 
 

@@ -108,16 +108,20 @@ def test_cn_stage_tiles(precision, tiles):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("nt", [64, 256, 2048, 8192])
-@pytest.mark.parametrize("terms", [wl.KERR, wl.ALL_TERMS & ~(wl.DIFFRACTION | wl.GVD), "kerr_n8"])
+@pytest.mark.parametrize("terms", [wl.KERR, wl.ALL_TERMS & ~(wl.DIFFRACTION | wl.GVD), "kerr_n8", "avalanche"])
 def test_nl_stage(precision, nt, terms):
-    """One nonlinear sub-step (Eq. nonlinearpart) against the oracle: Kerr only, every term, and
-    the whole Kerr sum to j = 4 (n2, n4, n6, n8) with every term."""
+    """One nonlinear sub-step (Eq. nonlinearpart) against the oracle: Kerr only, every term, the
+    whole Kerr sum to j = 4 (n2, n4, n6, n8) with every term, and every term with the avalanche
+    rate in the density equation."""
     say(f"nl stage {precision} nt={nt} terms={terms}")
     nr = 6
     inst = wl.config_full(nr=nr, nt=nt)
     if terms == "kerr_n8":
         inst.update(n6=wl.config_higher_kerr()["n6"], n8=wl.config_higher_kerr()["n8"])
         terms = wl.ALL_TERMS & ~(wl.DIFFRACTION | wl.GVD)
+    elif terms == "avalanche":
+        inst["U_i"] = wl.U_I_O2
+        terms = (wl.ALL_TERMS | wl.AVALANCHE) & ~(wl.DIFFRACTION | wl.GVD)
     inst["terms"] = terms
     rng = np.random.default_rng(nt)
     t = inst["t_min"] + np.arange(nt) * (inst["t_max"] - inst["t_min"]) / nt
@@ -241,6 +245,32 @@ def test_higher_order_kerr_and_chirp(precision, tol):
     off = dict(inst, n6=0.0, n8=0.0)
     assert werr(oracle.propagate(off, a_in.astype(np.complex128), 30), want) > 1e-3
     say(f"  higher-order Kerr + chirp {precision}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < (ELEMENTWISE * tol if k == "elementwise" else tol), (k, v)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32_cn64", 1e-5), ("fp32_storage", 1e-5)])
+def test_avalanche_ionisation_run(precision, tol):
+    """Avalanche ionisation (sigma_c / U_i) I rho added to the density rate, with every other term,
+    30 steps of 5 mm at 7e17 W/m^2 through the C ABI against the oracle: field, fluence and peak
+    density within the bound (element-wise within ELEMENTWISE times it); the avalanche moves the
+    oracle's own peak density by more than 1 %."""
+    inst = wl.config_avalanche(nr=96, nt=512)
+    a0 = wl.gaussian_field(inst)
+    a_in = a0 if precision == "fp64" else a0.astype(np.complex64)
+    got, plan = _run(inst, precision, 30, a0=a_in)
+    want = oracle.propagate(inst, a_in.astype(np.complex128), 30)
+    dg = oracle.diagnostics(inst, want)
+    g = got.astype(np.complex128)
+    d = plan.split_diag(plan.diagnostics(plan.pack(got)))[0]
+    errs = {"field": werr(g, want), "elementwise": relmax(g, want),
+            "fluence": float(np.max(np.abs(d["fluence"] - dg["fluence"])) / np.max(dg["fluence"])),
+            "rho_max": abs(d["rho_max"] / dg["rho_max"] - 1)}
+    off = dict(inst, terms=inst["terms"] & ~wl.AVALANCHE)
+    d_off = oracle.diagnostics(off, oracle.propagate(off, a_in.astype(np.complex128), 30))
+    assert dg["rho_max"] > 1.01 * d_off["rho_max"]
+    say(f"  avalanche {precision}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+        + f"; rho_max {dg['rho_max']:.3e} (without avalanche {d_off['rho_max']:.3e})")
     for k, v in errs.items():
         assert v < (ELEMENTWISE * tol if k == "elementwise" else tol), (k, v)
 

@@ -73,7 +73,8 @@ def test_plan_sizes_on_host(lib):
     ("r_max", -1.0, fcn.FCN_E_ARG),
     ("t_max", -1.0, fcn.FCN_E_ARG),
     ("K", 0, fcn.FCN_E_ARG),
-    ("terms", 64, fcn.FCN_E_ARG),
+    ("terms", 128, fcn.FCN_E_ARG),
+    ("terms", 64 | 63, fcn.FCN_E_ARG),   # the avalanche term without an ionisation potential
     ("dz", 0.0, fcn.FCN_E_ARG),          # fixed mode needs dz > 0
     ("sigma_K", -1.0, fcn.FCN_E_ARG),
     ("n2", float("nan"), fcn.FCN_E_ARG),

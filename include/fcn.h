@@ -111,7 +111,8 @@ typedef struct {
                                 or dz log: those calls run eagerly) */
     int32_t col_tile;        /* 0: auto; else frequency pairs (p, nt - p) per column workgroup
                                 (1, 2, 4, 8, 16 or 32) */
-    int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (8 or 16) */
+    int32_t col_rows;        /* 0: auto; else rows per thread in the column solve (6, 8 or 16;
+                                6 with at most 8 pairs per workgroup) */
     int32_t lanes;           /* 0 or 1: every instance on the bound stream.  2..8: the instances
                                 are split into that many groups (greedy balance of nr * nt), each
                                 with its own launches and step counters, and fcn_step runs the

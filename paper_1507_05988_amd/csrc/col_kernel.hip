@@ -351,6 +351,12 @@ static hipError_t launch_col_p(int w, int l, int nr, const ColArgs &a, int grid,
     if (w == 16 && l == 8) return launch_col_t<R, ST, 16, 8>(nr, a, grid, s, e0, e1);
     if (w == 16 && l == 16) return launch_col_t<R, ST, 16, 16>(nr, a, grid, s, e0, e1);
     if (w == 32 && l == 8) return launch_col_t<R, ST, 32, 8>(nr, a, grid, s, e0, e1);
+    // 6 rows per thread: the FP64-arithmetic solve of a pair stays within 168 registers
+    // (three wavefronts per SIMD instead of two at 8 rows)
+    if (w == 1 && l == 6) return launch_col_t<R, ST, 1, 6>(nr, a, grid, s, e0, e1);
+    if (w == 2 && l == 6) return launch_col_t<R, ST, 2, 6>(nr, a, grid, s, e0, e1);
+    if (w == 4 && l == 6) return launch_col_t<R, ST, 4, 6>(nr, a, grid, s, e0, e1);
+    if (w == 8 && l == 6) return launch_col_t<R, ST, 8, 6>(nr, a, grid, s, e0, e1);
     return hipErrorInvalidValue;
 }
 

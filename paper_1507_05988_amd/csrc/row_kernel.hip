@@ -534,18 +534,32 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     const int tid = threadIdx.x;
     const int tr = tid % T;
     const int rw = tid / T;
-    const int item_idx = blockIdx.x * RPW + rw;
+    c2<R> *row_lds = lds + rw * Cfg::LROW;
+    // every row of a launch has the same nt, so one twiddle table serves them all: it is staged
+    // in LDS once per workgroup, and the workgroup then steps through its rows (groups of RPW
+    // rows blockIdx.x, blockIdx.x + gridDim.x, ...)
+    const c2<R> *tw = reinterpret_cast<const c2<R> *>(a.twiddle) + a.inst[a.items[0].inst].tw_off;
+    const c2<R> *twp = tw;
+    if constexpr (FFTS && Cfg::TW_LDS) {
+        for (int i = tid; i < NT / 2; i += Cfg::THREADS) {
+            twl[lpad(i)] = tw[i];
+            if constexpr (Cfg::PAIR) twl[lpad(NT / 2 + i)] = tw[NT + i];  // low parts: table of NT after the NT highs
+        }
+        __syncthreads();
+        twp = twl;
+    }
+    int64_t n = 0;
+    if constexpr (BOOK) n = a.state->cnt_row;
+
+    for (int grp = blockIdx.x; grp * RPW < a.nitems; grp += gridDim.x) {
+    const int item_idx = grp * RPW + rw;
     const bool active = item_idx < a.nitems;
     const RowItem it = a.items[active ? item_idx : 0];
     const DevInst in = a.inst[it.inst];
-    c2<R> *row_lds = lds + rw * Cfg::LROW;
     c2<ST> *g = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + (int64_t)it.m * NT;
-    const c2<R> *tw = reinterpret_cast<const c2<R> *>(a.twiddle) + in.tw_off;
 
-    int64_t n = 0;
     double dz_a = 0.0, dz_b = 0.0;
     if constexpr (BOOK) {
-        n = a.state->cnt_row;
         if constexpr ((FLAGS & RK_NL_A) != 0) dz_a = a.dz_ring[((n - 1) & 1) * a.batch + it.inst];
         if constexpr ((FLAGS & RK_NL_B) != 0) {
             if (a.dz_mode == DZ_ADAPTIVE) {
@@ -563,16 +577,6 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     c2<R> v[E];
 #pragma unroll
     for (int k = 0; k < E; k++) v[k] = active ? ccast<R, ST>(g[tr + k * T]) : czero<R>();
-
-    const c2<R> *twp = tw;
-    if constexpr (FFTS && Cfg::TW_LDS) {
-        for (int i = tid; i < NT / 2; i += Cfg::THREADS) {
-            twl[lpad(i)] = tw[i];
-            if constexpr (Cfg::PAIR) twl[lpad(NT / 2 + i)] = tw[NT + i];  // low parts: table of NT after the NT highs
-        }
-        __syncthreads();
-        twp = twl;
-    }
 
     if constexpr ((FLAGS & RK_IFFT_IN) != 0) {
         row_fft<R, NT, E, +1, Cfg::TW_LDS, Cfg::PAIR>(v, row_lds, tr, twp);
@@ -660,6 +664,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
                     a.dz_log[(n - a.log_base) * a.batch + it.inst] = dz_b;
             }
         }
+    }
+    }  // rows of this workgroup
+    if constexpr (BOOK) {
         if (blockIdx.x == 0 && tid == 0) a.state->cnt_col = n;
     }
 }

@@ -42,6 +42,13 @@ constexpr double kPi = 3.14159265358979323846;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+#ifndef FCN_ROW_GROUPS
+#define FCN_ROW_GROUPS 1024
+#endif
+// Workgroups of a row-kernel launch at most (4 per CU of the 256; 1024 measured faster than
+// 2048, 4096 and one workgroup per row group on the batched sweep).
+constexpr int kRowGroups = FCN_ROW_GROUPS;
+
 struct RowBucket {
     int lane;
     int nt;
@@ -217,7 +224,8 @@ void round_unit_f32(double c, double s, float out[2]) {
 }
 
 bool col_tiles_supported(int w, int l) {
-    return ((w == 1 || w == 2 || w == 4 || w == 8 || w == 16) && (l == 8 || l == 16)) || (w == 32 && l == 8);
+    return ((w == 1 || w == 2 || w == 4 || w == 8 || w == 16) && (l == 8 || l == 16)) || (w == 32 && l == 8) ||
+           ((w == 1 || w == 2 || w == 4 || w == 8) && l == 6);
 }
 
 // Column tile choice: frequencies per workgroup W and rows per thread L.
@@ -422,8 +430,10 @@ fcn_status build_plan(fcn_plan_t p) {
             if (p->dinst[i].c_mpa != 0.0 || p->dinst[i].c_coll != 0.0 || p->dinst[i].need_rho != 0.0)
                 b.scan &= ~RK_NOABS;
         }
+        // the row kernel steps through row groups (blockIdx.x, + gridDim.x, ...), so a workgroup
+        // stages its twiddle table once for several rows: at most kRowGroups workgroups
         const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)));
-        b.grid = (b.nitems + rpw - 1) / rpw;
+        b.grid = std::min((b.nitems + rpw - 1) / rpw, kRowGroups);
         p->row_buckets.push_back(b);
     }
     // column work lists, one bucket per nr; tiles from the options, else the tune cache, else
@@ -798,7 +808,7 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
         delete p;
         return FCN_E_ARG;
     }
-    if (p->opt.col_rows && p->opt.col_rows != 8 && p->opt.col_rows != 16) {
+    if (p->opt.col_rows && p->opt.col_rows != 6 && p->opt.col_rows != 8 && p->opt.col_rows != 16) {
         delete p;
         return FCN_E_ARG;
     }

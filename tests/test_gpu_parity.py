@@ -90,7 +90,8 @@ def test_cn_stage(precision, nr):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("tiles", [(8, 8), (16, 16), (4, 16), (32, 8), (16, 8), (2, 8), (2, 16), (1, 8), (1, 16)])
+@pytest.mark.parametrize("tiles", [(8, 8), (16, 16), (4, 16), (32, 8), (16, 8), (2, 8), (2, 16), (1, 8), (1, 16),
+                                   (8, 6), (4, 6), (2, 6), (1, 6)])
 def test_cn_stage_tiles(precision, tiles):
     nr, nt = 120, 128  # W * ceil(nr/L) stays within 512 threads for every tile
     if precision == "fp64" and tiles[1] == 16:

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fcn_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "liborc.so")
 
-DIFFRACTION, GVD, KERR, PLASMA, MPA, COLL = 1, 2, 4, 8, 16, 32
+DIFFRACTION, GVD, KERR, PLASMA, MPA, COLL, AVALANCHE = 1, 2, 4, 8, 16, 32, 64
 
 
 class OrcParams(ctypes.Structure):
@@ -34,7 +34,7 @@ class OrcParams(ctypes.Structure):
         ("n2", ctypes.c_double), ("n4", ctypes.c_double), ("n6", ctypes.c_double), ("n8", ctypes.c_double),
         ("K", ctypes.c_int32),
         ("sigma_K", ctypes.c_double), ("rho_at", ctypes.c_double), ("sigma_c", ctypes.c_double),
-        ("terms", ctypes.c_uint32),
+        ("U_i", ctypes.c_double), ("terms", ctypes.c_uint32),
     ]
 
 
@@ -124,7 +124,7 @@ def params(inst: dict, terms: int | None = None) -> OrcParams:
         elif name in ("nr", "nt", "K"):
             setattr(p, name, int(inst[name]))
         else:
-            setattr(p, name, float(inst[name]))
+            setattr(p, name, float(inst.get(name, 0.0) if name == "U_i" else inst[name]))
     return p
 
 

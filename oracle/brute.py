@@ -99,8 +99,10 @@ def rho_rk4(inst, inten_row: np.ndarray) -> np.ndarray:
     if rho_at <= 0:
         return rho
 
+    aval = inst["sigma_c"] / inst["U_i"] if inst["terms"] & 64 else 0.0
+
     def f(i, r):
-        return beta / (K * HBAR * w0) * i ** K * (1 - r / rho_at)
+        return beta / (K * HBAR * w0) * i ** K * (1 - r / rho_at) + aval * i * r
 
     for q in range(nt - 1):
         i0, i1 = inten_row[q], inten_row[q + 1]

@@ -22,7 +22,9 @@
  *   - the plasma term uses omega_pe^2/omega0^2 = rho/rho_c;
  *   - RK4 mid-stage intensity is the mean of the two neighbouring grid intensities,
  *     rho = 0 at the first grid time, intensities taken before the update;
- *   - collisional absorption -(sigma_c/2) rho is an extra switchable term;
+ *   - collisional absorption -(sigma_c/2) rho is an extra switchable term, and so is
+ *     avalanche ionisation, a rate (sigma_c / U_i) I rho added to the density equation
+ *     (neither is in the paper);
  *   - DFT: forward exp(-i w t) unnormalised, inverse scaled by 1/Nt.
  * All arithmetic is IEEE double.  OpenMP splits rows or columns statically; the loop
  * bodies do not depend on the thread count, so results are bitwise identical for
@@ -47,6 +49,7 @@ typedef double complex cplx;
 #define ORC_PLASMA 8u
 #define ORC_MPA 16u
 #define ORC_COLL 32u
+#define ORC_AVAL 64u
 
 /* One pulse on its grid.  Field layout: complex [nr][nt], t contiguous, interleaved. */
 typedef struct {
@@ -56,6 +59,7 @@ typedef struct {
     double n2, n4, n6, n8;
     int32_t K;
     double sigma_K, rho_at, sigma_c;
+    double U_i; /* ionisation potential [J] of the avalanche rate */
     uint32_t terms;
 } orc_params;
 
@@ -92,6 +96,7 @@ static int bad_params(const orc_params *p)
     if (p->nt & (p->nt - 1)) return 1; /* radix-2 transform */
     if (!(p->r_max > 0.0) || !(p->t_max > p->t_min) || !(p->lambda0 > 0.0) || !(p->n0 > 0.0)) return 1;
     if (p->K < 1) return 1;
+    if ((p->terms & ORC_AVAL) && !(p->U_i > 0.0)) return 1;
     return 0;
 }
 
@@ -261,11 +266,14 @@ int orc_cn_columns(const orc_params *pp, double *field, double dz, int nthreads)
 /* --------------------------------------------- nonlinear half step (Sec. 3.2) */
 
 /* Right-hand side of the rate equation (Eq. ionization):
- * d rho/dt = beta^(K) / (K hbar w0) |A|^{2K} (1 - rho/rho_at). */
+ * d rho/dt = beta^(K) / (K hbar w0) |A|^{2K} (1 - rho/rho_at), plus the avalanche rate
+ * (sigma_c / U_i) |A|^2 rho when that term is switched on. */
 static double rate(const orc_params *pp, const orc_derived *dv, double intensity, double rho)
 {
     double coef = dv->betaK / ((double)pp->K * ORC_HBAR * dv->w0);
-    return coef * pow(intensity, (double)pp->K) * (1.0 - rho / pp->rho_at);
+    double r = coef * pow(intensity, (double)pp->K) * (1.0 - rho / pp->rho_at);
+    if (pp->terms & ORC_AVAL) r += pp->sigma_c / pp->U_i * intensity * rho;
+    return r;
 }
 
 /* Electron density along one row by classical RK4 in t, starting from rho = 0 at the

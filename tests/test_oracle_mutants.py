@@ -35,6 +35,10 @@ MUTANTS = [
     ("kerr_n8_dropped", "pp->n8 * pow(inten, 4.0)", "0.0 * pow(inten, 4.0)"),
     ("kerr_n6_power", "pp->n6 * pow(inten, 3.0)", "pp->n6 * pow(inten, 2.0)"),
     ("mpa_half_dropped", "nhat += -(dv->betaK / 2.0) * pow(", "nhat += -(dv->betaK) * pow("),
+    ("avalanche_sign", "r += pp->sigma_c / pp->U_i * intensity * rho;", "r -= pp->sigma_c / pp->U_i * intensity * rho;"),
+    ("avalanche_no_intensity", "r += pp->sigma_c / pp->U_i * intensity * rho;", "r += pp->sigma_c / pp->U_i * rho;"),
+    ("avalanche_saturated", "r += pp->sigma_c / pp->U_i * intensity * rho;",
+     "r += pp->sigma_c / pp->U_i * intensity * rho * (1.0 - rho / pp->rho_at);"),
 ]
 
 

@@ -551,3 +551,39 @@ def test_full_model_grid_density_instability_in_the_oracle(orc):
             bounded = bool(np.all(np.isfinite(rho)) and rho.min() >= 0 and rho.max() <= inst["rho_at"])
         assert bounded == stable
         assert bool(np.all(np.isfinite(out))) == stable
+
+
+# -------------------------------------------- avalanche ionisation (not in the paper)
+
+@pytest.mark.parametrize("x_mpi,x_av", [(0.05, 0.02), (0.01, 0.03), (0.2, 0.2 * 0.999)])
+def test_avalanche_constant_intensity_closed_form(orc, x_mpi, x_av):
+    """With the avalanche rate the density equation at constant intensity is
+    d rho/dt = g (rho_at - rho) + a rho, g = sigma_K I^K, a = sigma_c I / U_i: linear with the
+    fixed point rho* = g rho_at / (g - a).  Its classical RK4 step multiplies (rho - rho*) by the
+    degree-4 Taylor polynomial of e^{-x}, x = (g - a) dtau, so rho_p = rho* (1 - r4(x)^p) from
+    rho_0 = 0, growing without bound when the avalanche outruns the multiphoton depletion
+    (a > g).  Parameters are set through x_mpi = g dtau and x_av = a dtau."""
+    nt = 64
+    inst = wl.config_full(nr=4, nt=nt)
+    inst["terms"] |= wl.AVALANCHE
+    dtau = (inst["t_max"] - inst["t_min"]) / nt
+    I = (x_mpi / (inst["sigma_K"] * dtau)) ** (1.0 / inst["K"])
+    inst["U_i"] = inst["sigma_c"] * I * dtau / x_av
+    rho = orc.rho_row(inst, np.full(nt, I))
+    x = x_mpi - x_av
+    r4 = 1 - x + x ** 2 / 2 - x ** 3 / 6 + x ** 4 / 24
+    star = x_mpi * inst["rho_at"] / x
+    want = star * (1 - r4 ** np.arange(nt))
+    assert np.max(np.abs(rho - want)) <= 1e-12 * np.max(np.abs(want))
+    without = orc.rho_row(dict(inst, terms=inst["terms"] & ~wl.AVALANCHE), np.full(nt, I))
+    assert rho[-1] > 1.01 * without[-1]  # the avalanche term is resolved
+    if x_av > x_mpi:
+        assert rho[-1] > inst["rho_at"]  # growth past rho_at: the linear avalanche rate has no cap
+
+
+def test_avalanche_needs_the_ionisation_potential(orc):
+    inst = wl.config_full(nr=4, nt=16)
+    inst["terms"] |= wl.AVALANCHE
+    inst["U_i"] = 0.0
+    with pytest.raises(ValueError):
+        orc.rho_row(inst, np.full(16, 1e17))

@@ -186,7 +186,8 @@ def kernel_name(precision, launch):
         return f"row_kernel<{r}, {st}, {nt}, {e}, {flags}>"
     r = "float" if precision == "fp32" else "double"
     st = "double" if precision == "fp64" else "float"
-    return f"col_kernel<{r}, {st}, {launch['tile'][0]}, {launch['tile'][1]}>"
+    cart = "true" if launch["pass"] in ("col_x", "col_y") else "false"
+    return f"col_kernel<{r}, {st}, {launch['tile'][0]}, {launch['tile'][1]}, {cart}>"
 
 
 def sweep_run(torch, insts, precision, steps, warmup, tune_cache, lanes, graph=True):
@@ -300,6 +301,46 @@ def paper_shapes_measurement(torch, tune_cache):
             rec[prec] = {"seconds_per_step": sec / timed, "seconds_for_paper_steps": sec / timed * nz,
                          "value": round(pts * timed / sec, 1), "col_tile": [t["col_tile"], t["col_rows"]]}
         out[name] = rec
+    return out
+
+
+def cartesian_measurement(torch, tune_cache, steps=100):
+    """The Cartesian 3D+1 multi-filament pulse (255 x 255 x 256 = 1.66e7 points, full model,
+    Delta_perp = d2/dx2 + d2/dy2): step rate of each precision over `steps` steps of 1 cm from the
+    noisy beam, mean per-launch kernel times (row pass, x solves, y solves; each pass reads and
+    writes the field once, 48 B per point-step in FP32), and the field error of the FP32-field
+    modes against the FP64 run after those steps (relative L2)."""
+    from paper_1507_05988_amd import fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    inst = wl.config_cartesian()
+    pts = wl.points(inst)
+    a0 = wl.cartesian_field(inst)
+    out = {"grid": f"{inst['nx']}x{inst['ny']}x{inst['nt']}", "points": pts, "steps": steps,
+           "z_m": steps * inst["dz"], "bytes_per_point_step": {"fp32_field": 48, "fp64_field": 96}}
+    fields = {}
+    for prec in ("fp32_cn64", "fp64", "fp32", "fp32_storage"):
+        plan = fcn.Plan(inst, precision=prec, tune_cache=tune_cache)
+        init = plan.pack(a0 if prec == "fp64" else a0.astype(np.complex64))
+        f = init.clone()
+        plan.step(f, 3)
+        launches = plan.step_timed_launches(f, 10)
+        sec = timed_steps(plan, f, init, steps, torch, chunk=steps)
+        plan.sync()
+        fields[prec] = plan.unpack(f)[0]
+        v = pts * steps / sec
+        bpp = 96 if prec == "fp64" else 48
+        out[prec] = {"value": round(v, 1), "ms_per_step": round(sec * 1e3 / steps, 4),
+                     "gbs_algorithmic": round(v * bpp / 1e9, 1),
+                     "launches": [{"pass": L["pass"], "size": L["size"], "tile": L["tile"], "ms": round(L["ms"], 6),
+                                   "gbs": round(L["points"] * bpp / 3 / (L["ms"] * 1e-3) / 1e9, 1)}
+                                  for L in launches]}
+        del plan, init, f
+    ref = fields["fp64"]
+    nref = np.linalg.norm(ref.ravel())
+    for prec in ("fp32_cn64", "fp32", "fp32_storage"):
+        out[prec]["field_err_vs_fp64"] = float(np.linalg.norm((fields[prec].astype(np.complex128) - ref).ravel()) / nref)
+    out["fp32_cn64"]["vs_fp64"] = round(out["fp32_cn64"]["value"] / out["fp64"]["value"], 3)
     return out
 
 
@@ -632,6 +673,7 @@ def main():
     ap.add_argument("--no-net", action="store_true")
     ap.add_argument("--no-paper-shapes", action="store_true")
     ap.add_argument("--no-long-pulse", action="store_true")
+    ap.add_argument("--no-cartesian", action="store_true")
     ap.add_argument("--long-pulse-checkpoints", default="100,1000,10000",
                     help="comma-separated step counts of the long-distance pulse checkpoints")
     ap.add_argument("--only-net", action="store_true",
@@ -758,6 +800,8 @@ def main():
             out["full_model_pulse"] = full_model_measurement(torch, args)
         if not args.no_paper_shapes:
             out["paper_shapes"] = paper_shapes_measurement(torch, args.tune_cache)
+        if not args.no_cartesian:
+            out["cartesian_3d"] = cartesian_measurement(torch, args.tune_cache)
         if not args.no_long_pulse:
             out["long_pulse"] = long_pulse_measurement(torch, [int(x) for x in args.long_pulse_checkpoints.split(",")])
         if not args.no_parareal:

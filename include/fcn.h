@@ -15,7 +15,10 @@
  *    instances of a plan; instance i starts at the element offset fcn_field_offset(i) and
  *    is a row-major [nr][nt] matrix with t contiguous: element (m, p) is A(r_m, t_p) with
  *    r_m = m r_max/(nr-1) and t_p = t_min + p (t_max - t_min)/nt (Sec. 3, the grid
- *    A_{m,p}).  Precision FCN_FP64 uses double2 elements, the FP32 modes float2 elements.
+ *    A_{m,p}).  A Cartesian instance (FCN_CARTESIAN) is a row-major [ny][nx][nt] array:
+ *    element (j, i, p) is A(x_i, y_j, t_p) with x_i = -x_max + i dx, dx = 2 x_max/(nx-1),
+ *    y_j likewise; its nx * ny transverse points play the part of the rows.
+ *    Precision FCN_FP64 uses double2 elements, the FP32 modes float2 elements.
  *    Between calls the field is in the time domain at an integer z-step.
  *  - Ownership: the caller allocates and frees every device buffer (field, workspace,
  *    diagnostics, dz log) and owns the HIP stream.  After fcn_plan_bind the library never
@@ -65,6 +68,18 @@ enum {
                             rate of Eq. ionization (not in the paper) */
 };
 
+/* Transverse geometry of an instance.  FCN_RADIAL: Delta_perp = d2/dr2 + (1/r) d/dr for a
+ * cylindrically symmetric beam, the case the paper discretises (Sec. 3.1).  FCN_CARTESIAN:
+ * Delta_perp = d2/dx2 + d2/dy2, the other operator named beside Eq. nlse (Sec. 2), which the
+ * paper does not discretise; here every frequency column takes the paper's Crank-Nicholson
+ * scheme along x and then along y, (1 - dz/2 Ly)^-1 (1 + dz/2 Ly) (1 - dz/2 Lx)^-1
+ * (1 + dz/2 Lx), with Lu = (i/2k0) d2/du2 + i k'' omega_p^2 / 4 (the GVD term split evenly);
+ * the two axis operators commute, so this is the Peaceman-Rachford alternating-direction form
+ * of the two-dimensional Crank-Nicholson step, and each factor is a tridiagonal solve per line.
+ * A = 0 on the four walls x = +-x_max, y = +-y_max (the counterpart of A = 0 at r_max, Eq.
+ * bound).  The transforms and the nonlinear half steps are the same as for FCN_RADIAL. */
+enum { FCN_RADIAL = 0, FCN_CARTESIAN = 1 };
+
 /* Precision modes.  FCN_FP32_STORAGE keeps the field in FP32 (the HBM traffic of FCN_FP32)
  * and computes every stage in FP64 inside the kernels: only the two FP32 stores per step
  * round, so the error grows like a random walk instead of accumulating the FP32 transform
@@ -77,9 +92,10 @@ enum { FCN_FP64 = 0, FCN_FP32 = 1, FCN_FP32_STORAGE = 2, FCN_FP32_CN64 = 3 };
 
 /* One pulse and its grid. */
 typedef struct {
-    int32_t nr;              /* radial points, 3 <= nr <= 4096; row nr-1 is r = r_max (A = 0) */
+    int32_t nr;              /* radial points, 3 <= nr <= 4096; row nr-1 is r = r_max (A = 0).
+                                FCN_CARTESIAN: the x points nx, 3 <= nx <= 4096 */
     int32_t nt;              /* time points, a power of two in [64, 8192] */
-    double r_max;            /* [m] */
+    double r_max;            /* [m]; FCN_CARTESIAN: the x half-width x_max */
     double t_min, t_max;     /* [s]; periodic window, t_max excluded */
     double lambda0;          /* carrier wavelength [m] */
     double n0;               /* linear refractive index */
@@ -92,6 +108,10 @@ typedef struct {
     double U_i;              /* ionisation potential [J] of the avalanche rate (> 0 with FCN_AVALANCHE) */
     double dz;               /* step length [m] (fixed mode), ignored when adaptive */
     uint32_t terms;          /* OR of the FCN_* term switches */
+    int32_t geometry;        /* FCN_RADIAL (0) or FCN_CARTESIAN */
+    int32_t ny;              /* FCN_CARTESIAN: y points, 3 <= ny <= 4096, nx * ny <= 2^22
+                                (ignored for FCN_RADIAL) */
+    double y_max;            /* FCN_CARTESIAN: the y half-width [m] (ignored for FCN_RADIAL) */
 } fcn_instance;
 
 typedef struct {
@@ -129,11 +149,14 @@ typedef struct {
                                 Read by fcn_plan_create (FCN_E_ARG if unreadable or malformed). */
 } fcn_options;
 
-/* Number of doubles per instance in one diagnostics record: 8 scalars then nr fluence values.
- * Scalars: [0] energy 2 pi dr^2 dtau (sum_p |A_0p|^2 / 8 + sum_m m sum_p |A_mp|^2) [J],
- * [1] peak intensity, [2] on-axis peak intensity [W/m^2], [3] peak electron density [m^-3],
- * [4] peak nonlinear phase rate Phi [rad/m], [5] z [m], [6] step index, [7] dz of the next step;
- * then fluence F(r_m) = dtau sum_p |A_mp|^2 [J/m^2] for m < nr. */
+/* Number of doubles per instance in one diagnostics record: 8 scalars then one fluence value
+ * per row (nr; nx * ny for FCN_CARTESIAN).
+ * Scalars: [0] energy 2 pi dr^2 dtau (sum_p |A_0p|^2 / 8 + sum_m m sum_p |A_mp|^2) [J]
+ * (FCN_CARTESIAN: dx dy dtau sum |A|^2), [1] peak intensity, [2] on-axis peak intensity [W/m^2]
+ * (FCN_CARTESIAN: at the point ((nx-1)/2, (ny-1)/2), x = y = 0 for odd nx and ny),
+ * [3] peak electron density [m^-3], [4] peak nonlinear phase rate Phi [rad/m], [5] z [m],
+ * [6] step index, [7] dz of the next step; then fluence F = dtau sum_p |A_.p|^2 [J/m^2] of
+ * every row (r_m for m < nr; the transverse point (i, j) at j nx + i for FCN_CARTESIAN). */
 #define FCN_DIAG_SCALARS 8
 
 /* Validates the instances and options and builds the host-side plan (derived constants,
@@ -150,7 +173,8 @@ fcn_status fcn_plan_workspace_size(fcn_plan_t plan, size_t *bytes);
 fcn_status fcn_field_size(fcn_plan_t plan, size_t *elems);
 fcn_status fcn_field_offset(fcn_plan_t plan, int32_t instance, size_t *elem_offset);
 
-/* Doubles of one diagnostics record for the whole batch: sum_i (FCN_DIAG_SCALARS + nr_i). */
+/* Doubles of one diagnostics record for the whole batch: sum_i (FCN_DIAG_SCALARS + rows_i),
+ * rows_i = nr_i (nx_i * ny_i for FCN_CARTESIAN). */
 fcn_status fcn_diag_record_size(fcn_plan_t plan, size_t *doubles);
 
 /* Attaches caller-owned device memory (workspace_dev, at least fcn_plan_workspace_size bytes,
@@ -162,8 +186,9 @@ fcn_status fcn_plan_bind(fcn_plan_t plan, void *workspace_dev, size_t workspace_
 /* Advances every instance by nsteps Strang steps (Sec. 3, Eq. nlseq):
  * A^{n+1} = NL(dz_n/2) o Linear(dz_n) o NL(dz_n/2) A^n, in place on field_dev.
  * The linear part is the forward FFT of every row, the Crank-Nicholson solve of every
- * frequency column (Eqs. matrix-matrix1, with c_j and f_j using (1 + 1/2j)) and the inverse
- * FFT (Eq. antifourier); the nonlinear half step integrates the electron density along t by
+ * frequency column (Eqs. matrix-matrix1, with c_j and f_j using (1 + 1/2j); FCN_CARTESIAN: one
+ * solve along x per (y line, frequency), then one along y per (x line, frequency)) and the
+ * inverse FFT (Eq. antifourier); the nonlinear half step integrates the electron density along t by
  * RK4 (Eq. ionization) from rho = 0 at t_min and multiplies by exp(dz/2 N) (Eqs. Anhalf,
  * Anhalf1, nonlinearpart).  nsteps >= 0.  Errors: FCN_E_STATE before bind. */
 fcn_status fcn_step(fcn_plan_t plan, void *field_dev, int64_t nsteps);
@@ -184,7 +209,7 @@ fcn_status fcn_diagnostics(fcn_plan_t plan, const void *field_dev, double *diag_
  * FCN_STAGE_FFT: forward FFT of every row (unnormalised, exp(-i omega t)).
  * FCN_STAGE_IFFT: inverse FFT of every row, scaled by 1/nt.
  * FCN_STAGE_CN: Crank-Nicholson solve of every frequency column over length `length`
- *   (field in the frequency domain).
+ *   (field in the frequency domain; FCN_CARTESIAN: the x solves, then the y solves).
  * FCN_STAGE_NL: one nonlinear sub-step A <- A exp(length N) (length = dz/2 for a half step). */
 enum { FCN_STAGE_FFT = 0, FCN_STAGE_IFFT = 1, FCN_STAGE_CN = 2, FCN_STAGE_NL = 3 };
 fcn_status fcn_stage(fcn_plan_t plan, int32_t stage, void *field_dev, double length);
@@ -211,10 +236,12 @@ fcn_status fcn_step_timed(fcn_plan_t plan, void *field_dev, int64_t nsteps, doub
 /* Per-launch kernel timing: like fcn_step_timed, and returns the mean duration [ms] of every
  * kernel launch of the steady step body (events recorded by the kernels themselves).  A step is
  * one row-pass launch per distinct nt of the plan (ascending nt), then one column-pass launch per
- * distinct nr (ascending nr): *n_launches of them.  launch_ms[l] receives the mean duration of
+ * distinct system length (ascending: nr of radial instances, then nx of the x solves, then ny of
+ * the y solves of Cartesian instances): *n_launches of them.  launch_ms[l] receives the mean duration of
  * launch l; launch_info[5 l .. 5 l + 4] receive {pass: 0 row, 1 column; its nt or nr; the grid
  * points the launch covers; elements per thread and rows per workgroup (row) or pair slots per
- * workgroup W and rows per thread L (column)}.  max_launches: capacity of the host arrays
+ * workgroup W and rows per thread L (column)}; the pass code is 2 for a Cartesian x solve and 3
+ * for a y solve.  max_launches: capacity of the host arrays
  * (launch_ms: max_launches, launch_info: 5 max_launches; FCN_E_SIZE, with *n_launches set,
  * when too small).  Synchronous; 2 <= nsteps <= 10000. */
 fcn_status fcn_step_timed_launches(fcn_plan_t plan, void *field_dev, int64_t nsteps, int32_t max_launches,

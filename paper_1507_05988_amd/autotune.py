@@ -33,6 +33,18 @@ CANDIDATES = {
 MAX_THREADS = 512
 
 
+def system_lengths(instances) -> set:
+    """Lengths of the column pass's tridiagonal systems: nr of a radial instance, nx and ny of
+    a Cartesian one (its x and y solves)."""
+    out = set()
+    for i in instances:
+        if i.get("geometry") == "cartesian":
+            out.update((int(i["nx"]), int(i["ny"])))
+        else:
+            out.add(int(i["nr"]))
+    return out
+
+
 def shape_key(instances, precision: str) -> str:
     shapes = sorted((int(i["nr"]), int(i["nt"])) for i in instances)
     return precision + "|" + ",".join(f"{nr}x{nt}" for nr, nt in shapes)
@@ -98,7 +110,7 @@ def tune(instances, precision: str = "fp32", steps: int = 20, repeats: int = 3, 
 
     if isinstance(instances, dict):
         instances = [instances]
-    nrs = sorted({int(i["nr"]) for i in instances})
+    nrs = sorted(system_lengths(instances))
     cache = load_cache(cache_path)
     if all((precision, nr) in cache for nr in nrs):
         per = {nr: {"col_tile": cache[(precision, nr)][0], "col_rows": cache[(precision, nr)][1],
@@ -106,7 +118,8 @@ def tune(instances, precision: str = "fp32", steps: int = 20, repeats: int = 3, 
         w0, l0 = per[nrs[-1]]["col_tile"], per[nrs[-1]]["col_rows"]
         return {"per_nr": per, "col_tile": w0, "col_rows": l0, "col_ms": None, "table": {}, "cached": True}
     dt = np.complex128 if precision == "fp64" else np.complex64
-    fields = [wl.gaussian_field(i, dt) if "I0" in i else wl.random_field(int(i["nr"]), int(i["nt"]), 0, dtype=dt)
+    fields = [wl.cartesian_field(i, dt) if fcn.is_cartesian(i) else
+              wl.gaussian_field(i, dt) if "I0" in i else wl.random_field(int(i["nr"]), int(i["nt"]), 0, dtype=dt)
               for i in instances]
     per_nr = {nr: {} for nr in nrs}      # nr -> {"WxL": us} where that bucket ran exactly W x L
 
@@ -122,7 +135,7 @@ def tune(instances, precision: str = "fp32", steps: int = 20, repeats: int = 3, 
         total = 0.0
         exact = True
         for j, launch in enumerate(runs[0]):
-            if launch["pass"] != "col":
+            if not launch["pass"].startswith("col"):
                 continue
             ms = float(np.median([r[j]["ms"] for r in runs]))
             total += ms
@@ -175,11 +188,11 @@ def main(argv=None):
     args = ap.parse_args(argv)
     # the headline workload last: where two workloads share an nr, its choice is the one kept
     work = {"full": [wl.config_full()], "long": [wl.config_long()], "application": [wl.config_paper_application()],
-            "timing": [wl.config_paper_timing()], "sweep": wl.config_batch()}
+            "timing": [wl.config_paper_timing()], "cartesian": [wl.config_cartesian()], "sweep": wl.config_batch()}
     cache = load_cache(args.out)
     for prec in ("fp32_cn64", "fp32", "fp32_storage", "fp64"):
         for name, insts in work.items():
-            for nr in {int(i["nr"]) for i in insts}:
+            for nr in system_lengths(insts):
                 cache.pop((prec, nr), None)
             store_cache(args.out, cache)
             r = tune(insts, prec, steps=args.steps, repeats=args.repeats, cache_path=args.out)

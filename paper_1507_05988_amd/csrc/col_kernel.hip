@@ -32,6 +32,15 @@
 // No pivoting is needed: with W = diag(1/8, 1, 2, ...) the operator dz/2 L is
 // W-skew-Hermitian, so after the diagonal similarity W^(1/2) the matrix I - dz/2 L has
 // Hermitian part I, which keeps every elimination (any symmetric ordering) well posed.
+//
+// Cartesian instances (Delta_perp = d2/dx2 + d2/dy2, field [ny][nx][nt]): the same solver runs
+// once along x for every (y line, pair slot) and then along y for every (x line, pair slot), two
+// launches of the CART variant.  A system is one line of n = nx (or ny) points at the stride nt
+// (or nx nt) with
+//   rows 1 .. n-2:   a = c = -is, b = 1 + i(2s - g),  d = f = is, e = conj(b)
+//   rows 0 and n-1 (the walls, A = 0):  identity, right-hand side 0
+// s = dz/(4 k0 dx^2) (dy for y) and g = k'' omega_p^2 dz / 8, half the GVD term in each axis.
+// The axis operators are skew-Hermitian, so the unweighted matrix already has Hermitian part I.
 #include <hip/hip_ext.h>
 
 #include "fcn_internal.h"
@@ -66,7 +75,7 @@ __device__ __forceinline__ c2<R> cmsub(c2<R> a, c2<R> b, c2<R> c) {
 }
 
 // R: arithmetic precision; ST: storage precision of the spectrum (see the row kernel).
-template <typename R, typename ST, int W, int L>
+template <typename R, typename ST, int W, int L, bool CART>
 __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     static_assert(L >= 4, "at least two interior rows per chunk");
     extern __shared__ unsigned char smem_raw[];
@@ -79,7 +88,12 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const int tile = xcd * per + min(xcd, rem) + (b >> 3);
     const ColItem it = a.items[tile];
     const DevInst in = a.inst[it.inst];
-    const int nr = in.nr, nt = in.nt;
+    const int nt = in.nt;
+    // the system: nr unknowns at the element stride rs from the line's first element
+    const bool xdir = CART && a.dir == COL_X;
+    const int nr = CART ? (xdir ? in.nx : in.ny) : in.nr;
+    const int64_t rs = CART && !xdir ? (int64_t)in.nx * nt : (int64_t)nt;
+    const int64_t line_off = CART ? (xdir ? (int64_t)it.line * in.nx * nt : (int64_t)it.line * nt) : 0;
     const int t = threadIdx.x;
     const int pl = t % W;
     const int k = t / W;
@@ -109,14 +123,14 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
         dz = a.dz_ring[(n & 1) * a.batch + it.inst];
     }
     // q^2 = slot^2 for both columns (q = slot for p1 < nt/2, q = -nt/2 for p1 = nt/2)
-    const R s = R(dz * in.diff_unit);
+    const R s = R(dz * (CART && !xdir ? in.diff_unit_y : in.diff_unit));
     const R g = R((double)p1 * (double)p1 * in.gvd_unit * dz);
     const R bi_in = R(2) * s - g;      // Im b, interior rows
     const R bi_ax = R(4) * s - g;      // Im b, axis row
     const double *rc = a.rowcoef + 2 * (int64_t)in.rowcoef_off;
 
-    c2<ST> *col1 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + p1;
-    c2<ST> *col2 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + p2;
+    c2<ST> *col1 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + line_off + p1;
+    c2<ST> *col2 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + line_off + p2;
     const int m0 = k * L;
 
     // ---- load rows m0-1 .. m0+L (halo included) of both columns; rows outside [0, nr) read as 0
@@ -125,15 +139,20 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     for (int i = 0; i < L + 2; i++) {
         const int m = m0 - 1 + i;
         const bool in_range = live && m >= 0 && m < nr;
-        x1[i] = in_range ? col1[(int64_t)m * nt] : mk<ST>(ST(0), ST(0));
-        x2[i] = in_range ? col2[(int64_t)m * nt] : mk<ST>(ST(0), ST(0));
+        x1[i] = in_range ? col1[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
+        x2[i] = in_range ? col2[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
     }
 
     // Row m of M_abc as (l, b, u) = (i lr, 1 + i bi, i ur) and of M_def x, computed on the fly.
     // x[i + 1] holds row m0 + i.
     auto row_coef = [&](int i, R &lr, R &bi, R &ur) {
         const int m = m0 + i;
-        if (m == 0) {
+        if (CART) {
+            const bool inner = m > 0 && m < nr - 1;
+            lr = inner ? -s : R(0);
+            bi = inner ? bi_in : R(0);
+            ur = inner ? -s : R(0);
+        } else if (m == 0) {
             lr = R(0);
             bi = bi_ax;
             ur = R(-4) * s;
@@ -150,7 +169,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     // d x_{m-1} + e x_m + f x_{m+1} with d = -l, e = conj(b), f = -u (zero on the r_max row)
     auto rhs_of = [&](const c2<ST> (&x)[L + 2], int i, R lr, R bi, R ur) -> c2<R> {
         const int m = m0 + i;
-        if (m >= nr - 1) return czero<R>();
+        if (m >= nr - 1 || (CART && m <= 0)) return czero<R>();
         const c2<R> xm = ccast<R, ST>(x[i + 1]);
         c2<R> v = mk<R>(xm.x + bi * xm.y, xm.y - bi * xm.x);
         v = cadd<R>(v, cmul_i<R>(ccast<R, ST>(x[i]), -lr));
@@ -313,14 +332,15 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     for (int i = 0; i < L; i++) {
         const int m = m0 + i;
         if (live && m < nr) {
-            col1[(int64_t)m * nt] = ccast<ST, R>(o1[i]);
-            if (store2) col2[(int64_t)m * nt] = ccast<ST, R>(o2[i]);
+            col1[(int64_t)m * rs] = ccast<ST, R>(o1[i]);
+            if (store2) col2[(int64_t)m * rs] = ccast<ST, R>(o2[i]);
         }
     }
 
-    if (!a.use_stage_len && t == 0) {
+    // step bookkeeping by the last solve of the step (a Cartesian instance's y launch)
+    if (!a.use_stage_len && t == 0 && (!CART || a.dir == COL_Y)) {
         if (blockIdx.x == 0) a.state->cnt_row = n + 1;
-        if (it.p0 == 0) {
+        if (it.p0 == 0 && it.line == 0) {
             a.zpos[it.inst] += dz;
             a.phi_slot[((n + 1) & 1) * a.batch + it.inst] = 0ull;  // slot of A^{n-1}, consumed
         }
@@ -333,7 +353,12 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
     const size_t shm = 4 * sizeof(c2<R>) * (size_t)W * S;
-    hipExtLaunchKernelGGL((col_kernel<R, ST, W, L>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1, 0, a);
+    if (a.dir == COL_RADIAL)
+        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1,
+                              0, a);
+    else
+        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, true>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1,
+                              0, a);
     return hipGetLastError();
 }
 

@@ -13,11 +13,16 @@ constexpr int DIAG_SCALARS = 8;
 // Per-instance constants, computed once on the host in FP64 and uploaded with the plan.
 // The operator coefficients are pre-multiplied so a kernel needs no division:
 //   s_n     = dz_n * diff_unit          the CN off-diagonal scale dz/(4 k0 dr^2)
+//                                       (Cartesian: dz/(4 k0 dx^2); diff_unit_y for y)
 //   gamma_p = q_p^2 * dz_n * gvd_unit   the CN GVD term k'' omega_p^2 dz / 4
+//                                       (Cartesian: k'' omega_p^2 dz / 8 in each axis solve)
 //   Im N    = I (ck1 + I (ck2 + I (ck3 + I ck4))) + c_plasma rho
 //   Re N    = c_mpa I^(K-1) + c_coll rho
 struct DevInst {
-    int32_t nr, nt;
+    int32_t nr, nt;         // rows (nx * ny for a Cartesian instance) and time points
+    int32_t geom;           // 0: radial; 1: Cartesian, field [ny][nx][nt]
+    int32_t nx, ny;         // Cartesian grid (nx = nr, ny = 1 for a radial instance)
+    int32_t axis_row;       // row of the on-axis diagnostics (0; Cartesian ((ny-1)/2, (nx-1)/2))
     int64_t field_off;      // complex elements from the start of the field buffer
     int32_t row_base;       // first global row index (row diagnostics partials)
     int32_t diag_off;       // double offset of this instance in a diagnostics record
@@ -26,8 +31,10 @@ struct DevInst {
     uint32_t terms;
     int32_t K;
     double dz_fixed;
-    double diff_unit;       // 1/(4 k0 dr^2), 0 when diffraction is off
-    double gvd_unit;        // k'' (2 pi/(nt dtau))^2 / 4, 0 when GVD is off
+    double diff_unit;       // 1/(4 k0 dr^2) (Cartesian 1/(4 k0 dx^2)), 0 when diffraction is off
+    double diff_unit_y;     // Cartesian 1/(4 k0 dy^2), 0 when diffraction is off
+    double e_unit;          // energy per unit of the weighted sum: 2 pi dr^2 dtau, or dx dy dtau
+    double gvd_unit;        // k'' (2 pi/(nt dtau))^2 / 4 (Cartesian: / 8), 0 when GVD is off
     double dtau, dr;
     double ck1, ck2, ck3, ck4;  // (k0/n0) n_2j, 0 when Kerr is off
     double c_plasma;        // -k0/(2 rho_c), 0 when the plasma term is off
@@ -64,11 +71,17 @@ struct RowItem {
 };
 
 // Work item of the column pass: W pair slots [p0, p0+W) of one instance, slot s standing for
-// the frequency columns s and nt - s (slots beyond nt/2 are empty).
+// the frequency columns s and nt - s (slots beyond nt/2 are empty); for a Cartesian axis solve
+// also the line: the y index of an x solve, the x index of a y solve (0 for radial items).
 struct ColItem {
     int32_t inst;
     int32_t p0;
+    int32_t line;
+    int32_t pad;
 };
+
+// Systems of a column-pass launch: radial columns, or the x or y lines of Cartesian instances.
+enum : int { COL_RADIAL = 0, COL_X = 1, COL_Y = 2 };
 
 // Row-kernel stage flags (compile-time).
 enum : int {
@@ -124,6 +137,7 @@ struct ColArgs {
     double *zpos;
     DevState *state;
     int32_t use_stage_len;
+    int32_t dir;              // COL_RADIAL, COL_X or COL_Y (the launch's systems)
     double stage_len;
 };
 
@@ -131,6 +145,7 @@ struct ColArgs {
 // e0/e1: optional events recorded at the kernel's start and end (nullptr: none).
 hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs &a, int grid,
                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// nr: the length of the launch's systems (nr, nx or ny after a.dir).
 hipError_t launch_col(int precision, int w, int l, int nr, const ColArgs &a, int grid, hipStream_t s,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int row_rows_per_group(int nt, int elems);

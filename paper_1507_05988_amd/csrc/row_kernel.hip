@@ -764,7 +764,8 @@ hipError_t launch_row(int precision, int nt, int elems, int flags, const RowArgs
 // ------------------------------------------------------------------ small kernels
 
 // One workgroup per instance: reduces the per-row partials of the last row pass into a
-// diagnostics record (layout in include/fcn.h).
+// diagnostics record (layout in include/fcn.h): radial rows weighted by w_m (energy
+// 2 pi dr^2 dtau sum_m w_m sum_p |A|^2), Cartesian points by 1 (energy dx dy dtau sum |A|^2).
 __global__ void __launch_bounds__(256) finalize_kernel(const DevInst *insts, int batch, const double *row_diag,
                                                        const double *zpos, const double *dz_ring,
                                                        const DevState *state, double *out) {
@@ -775,7 +776,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(const DevInst *insts, int
     double *rec = out + in.diag_off;
     for (int m = threadIdx.x; m < in.nr; m += blockDim.x) {
         const double *rd = row_diag + 4 * (int64_t)(in.row_base + m);
-        const double w = m == 0 ? 0.125 : (double)m;
+        const double w = in.geom ? 1.0 : (m == 0 ? 0.125 : (double)m);  // radial: w_0 = 1/8, w_m = m
         e += w * rd[0];
         im = fmax(im, rd[1]);
         rm = fmax(rm, rd[2]);
@@ -798,9 +799,9 @@ __global__ void __launch_bounds__(256) finalize_kernel(const DevInst *insts, int
     }
     if (threadIdx.x == 0) {
         const int64_t n = state->cnt_row;
-        rec[0] = 2.0 * 3.14159265358979323846 * in.dr * in.dr * in.dtau * se[0];
+        rec[0] = in.e_unit * se[0];
         rec[1] = si[0];
-        rec[2] = row_diag[4 * (int64_t)in.row_base + 1];
+        rec[2] = row_diag[4 * (int64_t)(in.row_base + in.axis_row) + 1];
         rec[3] = sr[0];
         rec[4] = sp[0];
         rec[5] = zpos[i];

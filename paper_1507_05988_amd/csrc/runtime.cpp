@@ -24,6 +24,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fcn.h"
@@ -57,13 +58,19 @@ struct RowBucket {
                // term, else 0
     int item_off, nitems;
     int grid;
+    int64_t points;  // grid points of the launch
 };
 struct ColBucket {
     int lane;
-    int nr;
+    int dir;   // COL_RADIAL, COL_X or COL_Y
+    int nr;    // system length: nr, nx or ny
     int w, l;
     int item_off, nitems;
+    int64_t points;
 };
+
+// Rows of an instance as the row pass sees them: nr radii, or nx * ny transverse points.
+int rows_of(const fcn_instance &in) { return in.geometry == FCN_CARTESIAN ? in.nr * in.ny : in.nr; }
 
 }  // namespace
 
@@ -146,7 +153,13 @@ fcn_status hip_fail(fcn_plan_t p, hipError_t e, const char *what) {
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 const char *check_instance(const fcn_instance &in) {
-    if (in.nr < 3 || in.nr > 4096) return "nr must be in [3, 4096]";
+    if (in.geometry != FCN_RADIAL && in.geometry != FCN_CARTESIAN) return "unknown geometry";
+    if (in.nr < 3 || in.nr > 4096) return "nr (nx) must be in [3, 4096]";
+    if (in.geometry == FCN_CARTESIAN) {
+        if (in.ny < 3 || in.ny > 4096) return "ny must be in [3, 4096]";
+        if ((int64_t)in.nr * in.ny > (int64_t)1 << 22) return "nx * ny must be at most 2^22";
+        if (!(in.y_max > 0.0) || !std::isfinite(in.y_max)) return "y_max must be positive";
+    }
     if (!is_pow2(in.nt) || in.nt < 64 || in.nt > 8192) return "nt must be a power of two in [64, 8192]";
     if (!(in.r_max > 0.0) || !std::isfinite(in.r_max)) return "r_max must be positive";
     if (!(in.t_max > in.t_min) || !std::isfinite(in.t_max) || !std::isfinite(in.t_min)) return "t_max must exceed t_min";
@@ -318,7 +331,7 @@ fcn_status build_plan(fcn_plan_t p) {
     std::map<int, int> rc_off;
     int rc_rows = 0;
     for (const auto &in : p->insts)
-        if (!rc_off.count(in.nr)) {
+        if (in.geometry == FCN_RADIAL && !rc_off.count(in.nr)) {
             rc_off[in.nr] = rc_rows;
             rc_rows += in.nr;
         }
@@ -335,13 +348,19 @@ fcn_status build_plan(fcn_plan_t p) {
     size_t doff = 0;
     for (int i = 0; i < B; i++) {
         const fcn_instance &in = p->insts[i];
+        const bool cart = in.geometry == FCN_CARTESIAN;
+        const int rows = rows_of(in);
         DevInst d{};
-        d.nr = in.nr;
+        d.nr = rows;
         d.nt = in.nt;
+        d.geom = cart ? 1 : 0;
+        d.nx = in.nr;
+        d.ny = cart ? in.ny : 1;
+        d.axis_row = cart ? (in.ny - 1) / 2 * in.nr + (in.nr - 1) / 2 : 0;
         d.field_off = (int64_t)off;
         d.row_base = row;
         d.diag_off = (int)doff;
-        d.rowcoef_off = rc_off[in.nr];
+        d.rowcoef_off = cart ? 0 : rc_off[in.nr];
         d.tw_off = tw_off[in.nt];
         d.terms = in.terms;
         d.K = in.K;
@@ -350,11 +369,17 @@ fcn_status build_plan(fcn_plan_t p) {
         const double w0 = 2.0 * kPi * kC / in.lambda0;
         const double rho_c = kEps0 * kMe * w0 * w0 / (kQe * kQe);
         const double beta = (double)in.K * kHbar * w0 * in.sigma_K * in.rho_at;
-        d.dr = in.r_max / (double)(in.nr - 1);
+        // radial: dr = r_max/(nr-1); Cartesian: dx = 2 x_max/(nx-1), dy = 2 y_max/(ny-1)
+        d.dr = (cart ? 2.0 : 1.0) * in.r_max / (double)(in.nr - 1);
+        const double dy = cart ? 2.0 * in.y_max / (double)(in.ny - 1) : 0.0;
         d.dtau = (in.t_max - in.t_min) / (double)in.nt;
-        d.diff_unit = (in.terms & FCN_DIFFRACTION) ? 1.0 / (4.0 * k0 * d.dr * d.dr) : 0.0;
+        const bool diff = (in.terms & FCN_DIFFRACTION) != 0;
+        d.diff_unit = diff ? 1.0 / (4.0 * k0 * d.dr * d.dr) : 0.0;
+        d.diff_unit_y = diff && cart ? 1.0 / (4.0 * k0 * dy * dy) : 0.0;
+        d.e_unit = cart ? d.dr * dy * d.dtau : 2.0 * kPi * d.dr * d.dr * d.dtau;
         const double wu = 2.0 * kPi / ((double)in.nt * d.dtau);
-        d.gvd_unit = (in.terms & FCN_GVD) ? in.k2 * wu * wu / 4.0 : 0.0;
+        // the Cartesian step splits the GVD term evenly between its x and y solves
+        d.gvd_unit = (in.terms & FCN_GVD) ? in.k2 * wu * wu / (cart ? 8.0 : 4.0) : 0.0;
         const bool kerr = (in.terms & FCN_KERR) != 0;
         d.ck1 = kerr ? k0 / in.n0 * in.n2 : 0.0;
         d.ck2 = kerr ? k0 / in.n0 * in.n4 : 0.0;
@@ -385,9 +410,9 @@ fcn_status build_plan(fcn_plan_t p) {
         d.f_mpa = (float)(d.c_mpa * std::pow(iref, (double)(in.K - 1)));
         d.f_aval = (float)(d.c_aval * iref * d.dtau);
         p->dinst[i] = d;
-        off += (size_t)in.nr * in.nt;
-        row += in.nr;
-        doff += DIAG_SCALARS + in.nr;
+        off += (size_t)rows * in.nt;
+        row += rows;
+        doff += DIAG_SCALARS + rows;
     }
     p->field_elems = off;
     p->total_rows = row;
@@ -400,13 +425,13 @@ fcn_status build_plan(fcn_plan_t p) {
         std::vector<int> order(B);
         for (int i = 0; i < B; i++) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return (int64_t)p->insts[a].nr * p->insts[a].nt > (int64_t)p->insts[b].nr * p->insts[b].nt;
+            return (int64_t)rows_of(p->insts[a]) * p->insts[a].nt > (int64_t)rows_of(p->insts[b]) * p->insts[b].nt;
         });
         std::vector<int64_t> load(p->nlanes, 0);
         for (int i : order) {
             const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             p->lane_of[i] = l;
-            load[l] += (int64_t)p->insts[i].nr * p->insts[i].nt;
+            load[l] += (int64_t)rows_of(p->insts[i]) * p->insts[i].nt;
         }
     }
 
@@ -418,8 +443,11 @@ fcn_status build_plan(fcn_plan_t p) {
         b.lane = kv.first.first;
         b.nt = kv.first.second;
         b.item_off = (int)p->row_items.size();
-        for (int i : kv.second)
-            for (int m = 0; m < p->insts[i].nr; m++) p->row_items.push_back(RowItem{i, m});
+        b.points = 0;
+        for (int i : kv.second) {
+            for (int m = 0; m < rows_of(p->insts[i]); m++) p->row_items.push_back(RowItem{i, m});
+            b.points += (int64_t)rows_of(p->insts[i]) * p->insts[i].nt;
+        }
         b.nitems = (int)p->row_items.size() - b.item_off;
         // the density scan if any instance has a density term; otherwise the phase-only step
         // if no instance has an absorption term either
@@ -441,12 +469,23 @@ fcn_status build_plan(fcn_plan_t p) {
     std::map<int, std::pair<int, int>> cached;
     if (p->opt.tune_cache && !read_tune_cache(p->opt.tune_cache, p->precision, cached))
         return fail(p, FCN_E_ARG, "tune cache %s unreadable or malformed", p->opt.tune_cache);
-    std::map<std::pair<int, int>, std::vector<int>> by_nr;
-    for (int i = 0; i < B; i++) by_nr[{p->lane_of[i], p->insts[i].nr}].push_back(i);
+    // buckets keyed (lane, direction, system length): within a lane the radial solves, then the
+    // Cartesian x solves, then the y solves, which need the x solves' output
+    std::map<std::tuple<int, int, int>, std::vector<int>> by_nr;
+    for (int i = 0; i < B; i++) {
+        const fcn_instance &in = p->insts[i];
+        if (in.geometry == FCN_CARTESIAN) {
+            by_nr[{p->lane_of[i], (int)COL_X, in.nr}].push_back(i);
+            by_nr[{p->lane_of[i], (int)COL_Y, in.ny}].push_back(i);
+        } else {
+            by_nr[{p->lane_of[i], (int)COL_RADIAL, in.nr}].push_back(i);
+        }
+    }
     for (auto &kv : by_nr) {
         ColBucket b{};
-        b.lane = kv.first.first;
-        b.nr = kv.first.second;
+        b.lane = std::get<0>(kv.first);
+        b.dir = std::get<1>(kv.first);
+        b.nr = std::get<2>(kv.first);
         fcn_options o = p->opt;
         const auto hit = cached.find(b.nr);
         if (hit != cached.end()) {
@@ -457,9 +496,16 @@ fcn_status build_plan(fcn_plan_t p) {
         if (b.w * ((b.nr + b.l - 1) / b.l) > 512) return fail(p, FCN_E_SIZE, "nr=%d too large for the column solve", b.nr);
         if (!col_tiles_supported(b.w, b.l)) return fail(p, FCN_E_ARG, "column tile %dx%d not built", b.w, b.l);
         b.item_off = (int)p->col_items.size();
-        // pair slots s = 0 .. nt/2 (columns s and nt - s share their matrices), W per workgroup
-        for (int i : kv.second)
-            for (int s0 = 0; s0 <= p->insts[i].nt / 2; s0 += b.w) p->col_items.push_back(ColItem{i, s0});
+        // pair slots s = 0 .. nt/2 (columns s and nt - s share their matrices), W per workgroup;
+        // Cartesian: for every line of the other axis (y lines for the x solves, x for the y)
+        b.points = 0;
+        for (int i : kv.second) {
+            const fcn_instance &in = p->insts[i];
+            const int lines = b.dir == COL_X ? in.ny : (b.dir == COL_Y ? in.nr : 1);
+            for (int line = 0; line < lines; line++)
+                for (int s0 = 0; s0 <= in.nt / 2; s0 += b.w) p->col_items.push_back(ColItem{i, s0, line, 0});
+            b.points += (int64_t)rows_of(in) * in.nt;
+        }
         b.nitems = (int)p->col_items.size() - b.item_off;
         p->col_buckets.push_back(b);
         p->col_w = b.w;
@@ -578,6 +624,7 @@ hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0
         const auto &b = p->col_buckets[bi];
         if (lane >= 0 && b.lane != lane) continue;
         ColArgs a = col_args(p, field, b);
+        a.dir = b.dir;
         a.use_stage_len = stage;
         a.stage_len = stage_len;
         hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, lane_stream(p, lane),
@@ -820,7 +867,10 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
         const char *why = check_instance(inst[i]);
         if (why) {
             delete p;
-            return (inst[i].nr > 4096 || inst[i].nt > 8192) ? FCN_E_SIZE : FCN_E_ARG;
+            const bool big = inst[i].nr > 4096 || inst[i].nt > 8192 ||
+                             (inst[i].geometry == FCN_CARTESIAN &&
+                              (inst[i].ny > 4096 || (int64_t)inst[i].nr * inst[i].ny > (int64_t)1 << 22));
+            return big ? FCN_E_SIZE : FCN_E_ARG;
         }
         if (!p->opt.adaptive && !(inst[i].dz > 0.0)) {
             delete p;
@@ -1115,17 +1165,15 @@ fcn_status fcn_step_timed_launches(fcn_plan_t p, void *field_dev, int64_t nsteps
         int64_t pts = 0;
         if (l < nrow) {
             const auto &b = p->row_buckets[l];
-            for (int i = 0; i < p->batch; i++)
-                if (p->dinst[i].nt == b.nt && p->lane_of[i] == b.lane) pts += (int64_t)p->dinst[i].nr * p->dinst[i].nt;
+            pts = b.points;
             launch_info[5 * l] = 0;
             launch_info[5 * l + 1] = b.nt;
             launch_info[5 * l + 3] = row_elems_for(b.nt, row_fp64_arith(p->precision));
             launch_info[5 * l + 4] = row_rows_per_group(b.nt, (int)launch_info[5 * l + 3]);
         } else {
             const auto &b = p->col_buckets[l - nrow];
-            for (int i = 0; i < p->batch; i++)
-                if (p->dinst[i].nr == b.nr && p->lane_of[i] == b.lane) pts += (int64_t)p->dinst[i].nr * p->dinst[i].nt;
-            launch_info[5 * l] = 1;
+            pts = b.points;
+            launch_info[5 * l] = 1 + b.dir;
             launch_info[5 * l + 1] = b.nr;
             launch_info[5 * l + 3] = b.w;
             launch_info[5 * l + 4] = b.l;

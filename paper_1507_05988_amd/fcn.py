@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfcn.so")
 
 FCN_OK, FCN_E_ARG, FCN_E_SIZE, FCN_E_HIP, FCN_E_NONFINITE, FCN_E_STATE, FCN_E_UNSUPPORTED, FCN_E_UNSTABLE = range(8)
 FCN_FP64, FCN_FP32, FCN_FP32_STORAGE, FCN_FP32_CN64 = 0, 1, 2, 3
+GEOMETRY_RADIAL, GEOMETRY_CARTESIAN = 0, 1  # FCN_RADIAL, FCN_CARTESIAN
 PRECISIONS = {"fp64": FCN_FP64, "fp32": FCN_FP32, "fp32_storage": FCN_FP32_STORAGE, "fp32_cn64": FCN_FP32_CN64}
 STAGE_FFT, STAGE_IFFT, STAGE_CN, STAGE_NL = 0, 1, 2, 3
 DIAG_SCALARS = 8
@@ -52,6 +53,7 @@ class Instance(ctypes.Structure):
         ("sigma_K", ctypes.c_double), ("rho_at", ctypes.c_double), ("sigma_c", ctypes.c_double),
         ("U_i", ctypes.c_double), ("dz", ctypes.c_double),
         ("terms", ctypes.c_uint32),
+        ("geometry", ctypes.c_int32), ("ny", ctypes.c_int32), ("y_max", ctypes.c_double),
     ]
 
 
@@ -140,10 +142,34 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
+def is_cartesian(inst: dict) -> bool:
+    """A Cartesian instance dict has geometry "cartesian" and nx, ny, x_max, y_max in place of
+    nr and r_max (field [ny][nx][nt]); any other dict is radial (field [nr][nt])."""
+    return inst.get("geometry", "radial") == "cartesian"
+
+
+def field_shape(inst: dict) -> tuple:
+    nt = int(inst["nt"])
+    return (int(inst["ny"]), int(inst["nx"]), nt) if is_cartesian(inst) else (int(inst["nr"]), nt)
+
+
+def rows(inst: dict) -> int:
+    """Rows of the row pass: nr, or the nx * ny transverse points of a Cartesian instance."""
+    return int(inst["ny"]) * int(inst["nx"]) if is_cartesian(inst) else int(inst["nr"])
+
+
 def make_instance(inst: dict) -> Instance:
     c = Instance()
+    cart = is_cartesian(inst)
     for name, _ in Instance._fields_:
-        val = inst.get(name, 0.0) if name == "U_i" else inst[name]
+        if name == "geometry":
+            c.geometry = GEOMETRY_CARTESIAN if cart else GEOMETRY_RADIAL
+            continue
+        if name in ("ny", "y_max"):
+            setattr(c, name, (int if name == "ny" else float)(inst[name]) if cart else 0)
+            continue
+        key = {"nr": "nx", "r_max": "x_max"}.get(name, name) if cart else name
+        val = inst.get(key, 0.0) if name == "U_i" else inst[key]
         setattr(c, name, int(val) if name in ("nr", "nt", "K", "terms") else float(val))
     return c
 
@@ -155,7 +181,8 @@ class Plan:
     "fp32_storage" (FP32 field, FP64 arithmetic in the kernels) or "fp32_cn64" (FP32 field and
     row pass with twiddles as hi + lo pairs, FP64-arithmetic column solve).
     The field is one flat complex torch tensor on the device (complex128 for fp64, else complex64),
-    instance i occupying [offset(i), offset(i) + nr*nt) as a row-major [nr][nt] matrix.
+    instance i occupying [offset(i), offset(i) + nr*nt) as a row-major [nr][nt] matrix (a
+    Cartesian instance: nx*ny*nt elements, row-major [ny][nx][nt]).
     """
 
     def __init__(self, instances, precision: str = "fp64", adaptive: bool = False, max_phase: float = 0.05,
@@ -220,12 +247,13 @@ class Plan:
         return self.torch.zeros(self.field_elems, dtype=self.cdtype, device=self.device)
 
     def pack(self, fields) -> "torch.Tensor":
-        """List of [nr][nt] numpy arrays (one per instance) -> flat device field."""
+        """List of [nr][nt] (Cartesian: [ny][nx][nt]) numpy arrays, one per instance -> flat
+        device field."""
         if isinstance(fields, np.ndarray):
             fields = [fields]
         host = np.zeros(self.field_elems, dtype=np.complex128 if self.precision == "fp64" else np.complex64)
         for i, (f, inst) in enumerate(zip(fields, self.instances)):
-            n = int(inst["nr"]) * int(inst["nt"])
+            n = rows(inst) * int(inst["nt"])
             host[self.offsets[i]:self.offsets[i] + n] = np.asarray(f).reshape(-1)
         return self.torch.from_numpy(host).to(self.device)
 
@@ -233,8 +261,8 @@ class Plan:
         host = field.detach().to("cpu").numpy()
         out = []
         for i, inst in enumerate(self.instances):
-            nr, nt = int(inst["nr"]), int(inst["nt"])
-            out.append(host[self.offsets[i]:self.offsets[i] + nr * nt].reshape(nr, nt).copy())
+            n = rows(inst) * int(inst["nt"])
+            out.append(host[self.offsets[i]:self.offsets[i] + n].reshape(field_shape(inst)).copy())
         return out
 
     def _field_ptr(self, field):
@@ -281,15 +309,17 @@ class Plan:
 
     def step_timed_launches(self, field, nsteps: int):
         """Steps with HIP events around every launch; returns a list of dicts
-        {pass: "row"|"col", size: nt or nr, points, tile, ms} in launch order (tile: elements per
-        thread and rows per workgroup of a row launch, [W, L] of a column launch)."""
+        {pass: "row"|"col"|"col_x"|"col_y", size: nt or the system length, points, tile, ms} in
+        launch order (tile: elements per thread and rows per workgroup of a row launch, [W, L] of
+        a column launch; col_x / col_y: the x and y solves of Cartesian instances)."""
         cap = 64
         n = ctypes.c_int32()
         ms = (ctypes.c_double * cap)()
         info = (ctypes.c_int64 * (5 * cap))()
         self._check(self.lib.fcn_step_timed_launches(self._h, self._field_ptr(field), int(nsteps), cap,
                                                      ctypes.byref(n), ms, info))
-        return [{"pass": "row" if info[5 * i] == 0 else "col", "size": int(info[5 * i + 1]),
+        names = ("row", "col", "col_x", "col_y")
+        return [{"pass": names[info[5 * i]], "size": int(info[5 * i + 1]),
                  "points": int(info[5 * i + 2]), "tile": [int(info[5 * i + 3]), int(info[5 * i + 4])],
                  "ms": ms[i]} for i in range(n.value)]
 
@@ -306,7 +336,7 @@ class Plan:
         rec = record.detach().to("cpu").numpy() if hasattr(record, "detach") else np.asarray(record)
         out, off = [], 0
         for inst in self.instances:
-            nr = int(inst["nr"])
+            nr = rows(inst)
             d = {k: float(rec[off + j]) for j, k in enumerate(DIAG_NAMES)}
             d["fluence"] = rec[off + DIAG_SCALARS:off + DIAG_SCALARS + nr].copy()
             out.append(d)

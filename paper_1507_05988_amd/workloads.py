@@ -224,6 +224,50 @@ def config_paper_application(nr=1350, nt=1024) -> dict:
     return _pulse(inst, 18 * MM, 300 * FS, power / pcr)
 
 
+def config_cartesian(nx=255, ny=255, nt=256, p_over_pcr=30.0) -> dict:
+    """Cartesian 3D+1 pulse (Delta_perp = d2/dx2 + d2/dy2, Sec. 2): an elliptic Gaussian beam,
+    w_x = 3 mm, w_y = 2 mm, tau = 50 fs, `p_over_pcr` critical powers (I0 = 2P / (pi w_x w_y)),
+    on x, y in [-12, 12] mm (nx, ny points; odd counts put x = y = 0 on a grid point) and
+    t in [-200, 200) fs, the full-model coefficients, dz = 1 cm.  With the seeded transverse
+    noise of ``cartesian_field`` the beam breaks up into several filaments (the regime that needs
+    the Cartesian form)."""
+    wx, wy, tau = 3 * MM, 2 * MM, 50 * FS
+    inst = _base(3, nt, wx, tau, dz=1e-2, **FULL_PHYSICS)
+    del inst["nr"], inst["r_max"]
+    pcr = critical_power(inst["lambda0"], inst["n0"], inst["n2"])
+    inst.update(geometry="cartesian", nx=nx, ny=ny, x_max=12 * MM, y_max=12 * MM, wx=wx, wy=wy, tau=tau,
+                P=p_over_pcr * pcr, I0=2.0 * p_over_pcr * pcr / (math.pi * wx * wy), p_over_pcr=p_over_pcr,
+                chirp=0.0, noise=0.05, noise_seed=11)
+    return inst
+
+
+def cartesian_field(inst: dict, dtype=np.complex128) -> np.ndarray:
+    """Initial Cartesian pulse [ny][nx][nt]: sqrt(I0) exp(-x^2/wx^2 - y^2/wy^2 - t^2/tau^2)
+    times (1 + noise eta(x, y)), eta a seeded real Gaussian field smoothed over about 0.3 mm
+    (unit standard deviation); grid x_i = -x_max + i 2 x_max/(nx-1), y likewise,
+    t_p = t_min + p (t_max - t_min)/nt; the four walls are zero (A = 0 there)."""
+    nx, ny, nt = int(inst["nx"]), int(inst["ny"]), int(inst["nt"])
+    x = -inst["x_max"] + np.arange(nx) * (2.0 * inst["x_max"] / (nx - 1))
+    y = -inst["y_max"] + np.arange(ny) * (2.0 * inst["y_max"] / (ny - 1))
+    t = inst["t_min"] + np.arange(nt, dtype=np.float64) * ((inst["t_max"] - inst["t_min"]) / nt)
+    env = np.exp(-(y[:, None] / inst["wy"]) ** 2 - (x[None, :] / inst["wx"]) ** 2)
+    if inst.get("noise", 0.0) > 0.0:
+        rng = np.random.default_rng(int(inst.get("noise_seed", 0)))
+        white = rng.standard_normal((ny, nx))
+        kx = np.fft.fftfreq(nx, d=x[1] - x[0])
+        ky = np.fft.fftfreq(ny, d=y[1] - y[0])
+        corr = 0.3 * MM
+        filt = np.exp(-((kx[None, :] ** 2 + ky[:, None] ** 2) * (math.pi * corr) ** 2))
+        eta = np.real(np.fft.ifft2(np.fft.fft2(white) * filt))
+        eta /= np.std(eta)
+        env = env * (1.0 + inst["noise"] * eta)
+    temporal = np.exp(-(t / inst["tau"]) ** 2 - 1j * inst.get("chirp", 0.0) * (t / inst["tau"]) ** 2)
+    a = math.sqrt(inst["I0"]) * env[:, :, None] * temporal[None, None, :]
+    a[0], a[-1] = 0.0, 0.0
+    a[:, 0], a[:, -1] = 0.0, 0.0
+    return a.astype(dtype)
+
+
 def random_field(nr: int, nt: int, seed: int, scale: float = 1.0, dtype=np.complex128) -> np.ndarray:
     """Seeded complex normal field (stage tests on random spectra); last row zero."""
     rng = np.random.default_rng(seed)
@@ -235,4 +279,5 @@ def random_field(nr: int, nt: int, seed: int, scale: float = 1.0, dtype=np.compl
 def points(insts) -> int:
     if isinstance(insts, dict):
         insts = [insts]
-    return int(sum(int(i["nr"]) * int(i["nt"]) for i in insts))
+    return int(sum((int(i["nx"]) * int(i["ny"]) if i.get("geometry") == "cartesian" else int(i["nr"])) * int(i["nt"])
+                   for i in insts))

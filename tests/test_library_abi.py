@@ -3,6 +3,7 @@ invalid plans on the host (no GPU call is made by these tests)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -214,3 +215,46 @@ def test_step_scratch_rejects_on_the_host(lib):
     assert lib.fcn_step_scratch(h, None, 1, None) == fcn.FCN_E_ARG
     assert lib.fcn_step_scratch(h, ctypes.c_void_p(0x1000), -1, None) == fcn.FCN_E_ARG
     assert lib.fcn_plan_destroy(h) == 0
+
+
+def test_instance_struct_matches_the_header(tmp_path):
+    """The Python mirror of fcn_instance has the C struct's size and field offsets (gcc compiles
+    the public header and prints them)."""
+    fields = [name for name, _ in fcn.Instance._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fcn.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(fcn_instance));\n" +
+                   "".join(f"  printf(\"%zu\\n\", offsetof(fcn_instance, {n}));\n" for n in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got[0] == ctypes.sizeof(fcn.Instance)
+    assert got[1:] == [getattr(fcn.Instance, n).offset for n in fields]
+
+
+def test_cartesian_plan_sizes_on_host(lib):
+    """A Cartesian instance: nx * ny * nt field elements ([ny][nx][nt]), a diagnostics record of
+    8 + nx * ny doubles, beside a radial instance in the same plan; invalid Cartesian grids are
+    refused."""
+    cart = wl.config_cartesian(nx=31, ny=17, nt=64)
+    rad = wl.config_small(nr=40, nt=128)
+    rc, h = _create(lib, [rad, cart], precision=fcn.FCN_FP32_CN64)
+    assert rc == fcn.FCN_OK
+    sz = ctypes.c_size_t()
+    assert lib.fcn_field_size(h, ctypes.byref(sz)) == 0 and sz.value == 40 * 128 + 31 * 17 * 64
+    assert lib.fcn_field_offset(h, 1, ctypes.byref(sz)) == 0 and sz.value == 40 * 128
+    assert lib.fcn_diag_record_size(h, ctypes.byref(sz)) == 0 and sz.value == (8 + 40) + (8 + 31 * 17)
+    lib.fcn_plan_destroy(h)
+    for key, value, code in (("ny", 2, fcn.FCN_E_ARG), ("ny", 4097, fcn.FCN_E_SIZE), ("nx", 2, fcn.FCN_E_ARG),
+                             ("y_max", 0.0, fcn.FCN_E_ARG), ("x_max", -1.0, fcn.FCN_E_ARG)):
+        bad = dict(cart, **{key: value})
+        rc, h = _create(lib, [bad])
+        assert rc == code and not h.value, (key, value)
+    big = wl.config_cartesian(nx=4096, ny=1025, nt=64)  # more than 2^22 transverse points
+    assert _create(lib, [big])[0] == fcn.FCN_E_SIZE
+    inst = fcn.make_instance(cart)
+    inst.geometry = 2
+    arr = (fcn.Instance * 1)(inst)
+    o = fcn.Options(precision=0, max_phase=0.05, dz_min=1e-6, dz_max=1e-2)
+    assert lib.fcn_plan_create(arr, 1, ctypes.byref(o), ctypes.byref(ctypes.c_void_p())) == fcn.FCN_E_ARG

@@ -34,8 +34,12 @@ size_t conv5_mfma_weight_bytes(int Cin);
 hipError_t launch_pack_mfma_weights(const float *wr, void *wA, int Cin, hipStream_t s);
 hipError_t launch_conv5_mfma(const void *in, const void *wA, const float *bias, void *out, int B, int Cin, int Hin,
                              int Win, int Hout, int Wout, int relu, hipStream_t s);
-hipError_t launch_conv5_wgrad(int act_bf16, const void *in, const float *g, float *gw, float *gb, int B, int Cin,
-                              int Hin, int Win, int Cout, int Hout, int Wout, hipStream_t s);
+// Weight and bias gradients of a 5x5 layer.  part: NULL, or conv5_wgrad_part_floats(B, Cin, Cout)
+// floats of scratch, which selects the matrix-core form for square layers of 16, 32, 48 or 64
+// real channels (0 floats: the vector kernel is used).
+size_t conv5_wgrad_part_floats(int B, int Cin, int Cout);
+hipError_t launch_conv5_wgrad(int act_bf16, const void *in, const float *g, float *gw, float *gb, float *part, int B,
+                              int Cin, int Hin, int Win, int Cout, int Hout, int Wout, hipStream_t s);
 hipError_t launch_relu_mask(int act_bf16, float *g, const void *act, size_t n, hipStream_t s);
 hipError_t launch_expand_weights(const float *pc, float *wr, float *br, int cout, int cin, hipStream_t s);
 hipError_t launch_flip_transpose(const float *w, float *wt, int cout, int cin, hipStream_t s);

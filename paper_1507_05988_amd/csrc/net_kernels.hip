@@ -275,6 +275,96 @@ __global__ void __launch_bounds__(256) conv5_wgrad_kernel(const AI *__restrict__
     if (threadIdx.x == 25 && ci == 0 && gb) gb[co] = red[0][25];
 }
 
+// Weight gradient of a layer with Ci = Co = 16 NT real channels on the matrix cores:
+// gw[co][ci][5 ky + kx] = sum_{b, y, x} g[b][co][y][x] in[b][ci][y + ky][x + kx] as 25 GEMMs
+// (m = co, n = ci, k = output pixel), one v_mfma_f32_16x16x4_f32 per 16 co x 16 ci x 4 pixels:
+// FP32 operands and accumulation, so the products and sums are those of the vector kernel
+// above up to the order of the additions.  Operand layout of that instruction (lane l):
+// A[m = l % 16][k = l / 16], B[k = l / 16][n = l % 16], D[m = 4 (l / 16) + i][n = l % 16], i < 4.
+// Workgroup (b, ky): image b and kernel row ky; NT waves, wave w the output channels
+// 16 w .. 16 w + 15 against all NT input-channel tiles and the 5 taps kx (5 NT accumulator tiles).
+// Per segment of 64 pixels of an output row y the workgroup stages g[b][.][y][.] and
+// in[b][.][y + ky][.] (with the 4-pixel halo) in LDS as FP32 [channel][x] (odd pitches; zero
+// gradient beyond Wout), then runs its MFMAs over the segment's pixels.  The workgroups with ky = 0 also sum g per channel (bias).
+// Partial sums go to part[b][ky][co][ci][kx] and part_b[b][co]; conv5_wgrad_reduce_kernel adds
+// the images in a fixed order, so the result is deterministic.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+template <typename AI, int NT>
+__global__ void __launch_bounds__(256) conv5_wgrad_mfma_kernel(const AI *__restrict__ in, const float *__restrict__ g,
+                                                               float *__restrict__ part, float *__restrict__ part_b,
+                                                               int Hin, int Win, int Hout, int Wout) {
+    constexpr int C = 16 * NT;
+    constexpr int XS = 64;               // pixels of a row segment
+    constexpr int GP = XS + 1, IP = XS + 5;  // odd pitches
+    __shared__ float gs[C * GP];         // g[b][c][y][x0 + x], x < XS
+    __shared__ float is[C * IP];         // in[b][c][y + ky][x0 + x], x < XS + 4
+    const int b = blockIdx.x / 5, ky = blockIdx.x % 5;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    f32x4v acc[NT][5];
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+        for (int kx = 0; kx < 5; kx++) acc[t][kx] = f32x4v{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    const int m = lane & 15, kq = lane >> 4;
+    for (int y = 0; y < Hout; y++) {
+        for (int x0 = 0; x0 < Wout; x0 += XS) {
+            const int seg = min(XS, (Wout - x0 + 3) & ~3);  // a multiple of 4; zero gradient beyond Wout
+            __syncthreads();
+            for (int idx = tid; idx < C * XS; idx += 64 * NT) {
+                const int c = idx / XS, x = idx % XS, gx = x0 + x;
+                gs[c * GP + x] = gx < Wout ? g[(((size_t)b * C + c) * Hout + y) * Wout + gx] : 0.0f;
+            }
+            for (int idx = tid; idx < C * (XS + 4); idx += 64 * NT) {
+                const int c = idx / (XS + 4), x = idx % (XS + 4), gx = x0 + x;
+                is[c * IP + x] = gx < Win ? ld_act(in, (((size_t)b * C + c) * Hin + y + ky) * Win + gx) : 0.0f;
+            }
+            __syncthreads();
+            if (ky == 0 && tid < C)
+                for (int x = 0; x < XS; x++) bsum += gs[tid * GP + x];
+            for (int ks = 0; ks < seg / 4; ks++) {
+                const float a = gs[(16 * wave + m) * GP + 4 * ks + kq];
+#pragma unroll
+                for (int t = 0; t < NT; t++)
+#pragma unroll
+                    for (int kx = 0; kx < 5; kx++) {
+                        const float bv = is[(16 * t + m) * IP + 4 * ks + kq + kx];
+                        acc[t][kx] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[t][kx], 0, 0, 0);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+        for (int kx = 0; kx < 5; kx++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int co = 16 * wave + 4 * kq + i, ci = 16 * t + m;
+                part[((((size_t)b * 5 + ky) * C + co) * C + ci) * 5 + kx] = acc[t][kx][i];
+            }
+    if (ky == 0 && tid < C) part_b[(size_t)b * C + tid] = bsum;
+}
+
+// gw[co][ci][5 ky + kx] = sum_b part[b][ky][co][ci][kx], gb[co] = sum_b part_b[b][co], images in order.
+__global__ void conv5_wgrad_reduce_kernel(const float *__restrict__ part, const float *__restrict__ part_b,
+                                          float *__restrict__ gw, float *__restrict__ gb, int B, int C) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = C * C * 25;
+    if (idx < n) {
+        const int kx = idx % 5, ci = (idx / 5) % C, co = (idx / (5 * C)) % C, ky = idx / (5 * C * C);
+        float s = 0.0f;
+        for (int b = 0; b < B; b++) s += part[((((size_t)b * 5 + ky) * C + co) * C + ci) * 5 + kx];
+        gw[((size_t)co * C + ci) * 25 + 5 * ky + kx] = s;
+    } else if (idx < n + C && gb) {
+        const int co = idx - n;
+        float s = 0.0f;
+        for (int b = 0; b < B; b++) s += part_b[(size_t)b * C + co];
+        gb[co] = s;
+    }
+}
+
 // g[i] *= (act[i] > 0): gradient through ReLU, from the stored post-activation.
 template <typename A>
 __global__ void relu_mask_kernel(float *g, const A *act, size_t n) {
@@ -551,8 +641,41 @@ hipError_t launch_conv5_mfma(const void *in, const void *wA, const float *bias, 
     return hipGetLastError();
 }
 
-hipError_t launch_conv5_wgrad(int act_bf16, const void *in, const float *g, float *gw, float *gb, int B, int Cin,
-                              int Hin, int Win, int Cout, int Hout, int Wout, hipStream_t s) {
+size_t conv5_wgrad_part_floats(int B, int Cin, int Cout) {
+    return Cin == Cout && Cin % 16 == 0 && Cin <= 64 ? (size_t)B * 25 * Cin * Cin + (size_t)B * Cin : 0;
+}
+
+template <typename AI, int NT>
+static hipError_t launch_wgrad_mfma(const AI *in, const float *g, float *gw, float *gb, float *part, int B, int Hin,
+                                    int Win, int Hout, int Wout, hipStream_t s) {
+    constexpr int C = 16 * NT;
+    float *part_b = part + (size_t)B * 25 * C * C;
+    hipLaunchKernelGGL((conv5_wgrad_mfma_kernel<AI, NT>), dim3(B * 5), dim3(64 * NT), 0, s, in, g, part, part_b, Hin,
+                       Win, Hout, Wout);
+    const int n = C * C * 25 + C;
+    hipLaunchKernelGGL(conv5_wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part, part_b, gw, gb, B, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv5_wgrad(int act_bf16, const void *in, const float *g, float *gw, float *gb, float *part, int B,
+                              int Cin, int Hin, int Win, int Cout, int Hout, int Wout, hipStream_t s) {
+    // the matrix-core form when the partials buffer is there and the layer is square with a
+    // multiple of 16 channels (the hidden layers)
+    if (part && conv5_wgrad_part_floats(B, Cin, Cout)) {
+        const int nt = Cin / 16;
+        if (act_bf16) {
+            const bf16_t *x = (const bf16_t *)in;
+            if (nt == 1) return launch_wgrad_mfma<bf16_t, 1>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+            if (nt == 2) return launch_wgrad_mfma<bf16_t, 2>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+            if (nt == 3) return launch_wgrad_mfma<bf16_t, 3>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+            return launch_wgrad_mfma<bf16_t, 4>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+        }
+        const float *x = (const float *)in;
+        if (nt == 1) return launch_wgrad_mfma<float, 1>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+        if (nt == 2) return launch_wgrad_mfma<float, 2>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+        if (nt == 3) return launch_wgrad_mfma<float, 3>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+        return launch_wgrad_mfma<float, 4>(x, g, gw, gb, part, B, Hin, Win, Hout, Wout, s);
+    }
     if (act_bf16)
         hipLaunchKernelGGL(conv5_wgrad_kernel<bf16_t>, dim3(Cout * Cin), dim3(256), 0, s, (const bf16_t *)in, g, gw,
                            gb, B, Cin, Hin, Win, Cout, Hout, Wout);

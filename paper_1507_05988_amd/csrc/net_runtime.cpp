@@ -43,6 +43,7 @@ struct fcn_net_s {
     float *out = nullptr;     // FP32 [b][2][h][w]
     float *g[2];              // FP32 gradient ping-pong
     float *gout = nullptr;    // FP32 loss gradient [b][2][h][w]
+    float *wpart = nullptr;   // per-image partial weight gradients of the hidden layers (matrix-core form)
     double *nd = nullptr;     // loss partials [b][2]
     int *row0 = nullptr;      // loss row offsets [b]
     std::string err;
@@ -95,6 +96,7 @@ size_t layout(fcn_net_t n, int B, int H, int W, int training, unsigned char *p) 
     n->g[0] = (float *)take(gsz);
     n->g[1] = (float *)take(gsz);
     n->gout = (float *)take(training ? (size_t)B * 2 * H * W * 4 : 0);
+    n->wpart = (float *)take(training ? conv5_wgrad_part_floats(B, (int)C2, (int)C2) * 4 : 0);
     n->nd = (double *)take((size_t)B * 2 * 8);
     n->row0 = (int *)take((size_t)B * 4);
     return o;
@@ -266,8 +268,9 @@ fcn_status fcn_net_backward(fcn_net_t n, int32_t batch, int32_t h, int32_t w) {
         const int Hi = lin_h(l, h), Wi = lin_h(l, w), Ho = Hi - 4, Wo = Wi - 4;
         const int Ci = 2 * n->cin[l], Co = 2 * n->cout[l];
         // parameter gradients of layer l
-        e = launch_conv5_wgrad(n->act_bf16, n->act[l], gcur, n->gwr[l], n->gbr[l], batch, Ci, Hi, Wi, Co, Ho, Wo,
-                               n->stream);
+        e = launch_conv5_wgrad(n->act_bf16, n->act[l], gcur, n->gwr[l], n->gbr[l],
+                               conv5_wgrad_part_floats(batch, Ci, Co) ? n->wpart : nullptr, batch, Ci, Hi, Wi, Co, Ho,
+                               Wo, n->stream);
         if (e == hipSuccess)
             e = launch_contract_grads(n->gwr[l], n->gbr[l], n->grads + n->poff[l], n->cout[l], n->cin[l], n->stream);
         if (l == 0) break;

@@ -58,9 +58,14 @@ def _setup(C, bf16, B=3, H=12, W=20, seed=0):
 
 
 @pytest.mark.parametrize("bf16", [False, True])
-def test_network_forward_and_gradients_match_reference(bf16):
+@pytest.mark.parametrize("C,H,W", [(4, 12, 20), (8, 6, 60), (32, 8, 20)])
+def test_network_forward_and_gradients_match_reference(bf16, C, H, W):
+    """Forward, loss and every parameter gradient against the FP64 network oracle.  C = 8 and
+    C = 32 (16 and 64 real channels) take the matrix-core weight gradient of the hidden layers,
+    C = 8 with rows of 68 and 64 output pixels, so over two staged segments; C = 4 the vector
+    kernel."""
     import torch
-    C, B, H, W = 4, 3, 12, 20
+    B = 3
     net, smp, fdev, nr, nt, x, tgt, params, spec = _setup(C, bf16, B, H, W)
     net.input(fdev, smp, B, nr, nt, H, W)
     out = torch.zeros((B, 2, H, W), dtype=torch.float32, device=net.device)
@@ -80,7 +85,11 @@ def test_network_forward_and_gradients_match_reference(bf16):
     cos = float(g @ ref_g / (np.linalg.norm(g) * np.linalg.norm(ref_g)))
     say(f"  bf16={bf16}: forward {e_fwd:.2e}, loss {abs(loss / ref_loss - 1):.2e}, grads {e_g:.2e}, cosine {cos:.6f}")
     tol = 1e-2 if bf16 else 1e-5
-    assert e_fwd < tol and abs(loss / ref_loss - 1) < tol and e_g < tol
+    # BF16 at C = 32: the hidden layers run on the matrix cores with BF16-rounded weights as well
+    # as activations (forward 6e-3); the gradients combine two such rounded factors (measured
+    # 1.8e-2), while the FP32-activation run of the same network and kernels is at 4e-7
+    gtol = 2.5e-2 if bf16 and C == 32 else tol
+    assert e_fwd < tol and abs(loss / ref_loss - 1) < tol and e_g < gtol
     assert cos > (0.999 if bf16 else 1 - 1e-9)
 
 

@@ -635,7 +635,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
                 rd[2] = acc.rmax;
                 rd[3] = acc.phimax;
                 if (!(acc.sum <= 1.0e300)) atomicOr(&a.state->nonfinite, 1);  // NaN or overflow
-                if constexpr (BOOK) {
+                // the phase-rate slots feed the adaptive rule only; in the other modes the atomics
+                // (one per row, all rows of an instance on one address) would only cost time
+                if (BOOK && a.dz_mode == DZ_ADAPTIVE) {
                     atomicMax(&a.phi_slot[(n & 1) * a.batch + it.inst],
                               (unsigned long long)__double_as_longlong(acc.phimax));
                     if (a.seed_slots)

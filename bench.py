@@ -53,7 +53,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 COUNTER_FILE = os.path.join(ROOT, "profiles", "fcn_step_batched64_counters.json")
 # Column tiles per nr chosen by the autotuner on an MI355X (autotune.tune; regenerate with --retune)
 SHIPPED_TILES = os.path.join(ROOT, "paper_1507_05988_amd", "tuning", "mi355x_tiles.txt")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fcn_step_fullmodel_512x2048_traffic.json")
 
 
 def _sources_hash(paths):
@@ -76,24 +75,6 @@ def measured_counters(precision, kernel_name):
         for t in entries:
             if t["precision"] == precision and t["kernel"] == kernel_name:
                 return t if _sources_hash(t["sources"]) == t["sources_sha256"] else None
-    except (OSError, KeyError, ValueError):
-        pass
-    return None
-
-
-def measured_traffic(precision, kernel, tiles):
-    """HBM bytes per launch of one kernel of the full-model step (`kernel` "row" or "col") in
-    `precision` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or
-    None when no run covers that kernel or its sources changed since."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            entries = json.load(fh)["kernels"]
-        for t in entries:
-            if t["precision"] != precision or t["pass"] != kernel:
-                continue
-            if kernel == "col" and [t["col_tile"], t["col_rows"]] != [tiles["col_tile"], tiles["col_rows"]]:
-                continue
-            return int(t["bytes_per_launch"]) if _sources_hash(t["sources"]) == t["sources_sha256"] else None
     except (OSError, KeyError, ValueError):
         pass
     return None
@@ -601,8 +582,7 @@ def full_model_measurement(torch, args):
         out[prec] = {"value": round(pts * n / sec, 1), "ms_per_step": round(sec * 1e3 / n, 6),
                      "row_ms": round(krow, 6), "col_ms": round(kcol, 6),
                      "hbm_gbs_algorithmic": round(pts * n / sec * byt / 1e9, 1),
-                     "col_tile": [t["col_tile"], t["col_rows"]],
-                     "traffic_row": measured_traffic(prec, "row", t), "traffic_col": measured_traffic(prec, "col", t)}
+                     "col_tile": [t["col_tile"], t["col_rows"]]}
         del plan, f, init
     for prec in ("fp32_cn64", "fp32", "fp32_storage"):
         out[prec]["vs_fp64_plain"] = round(out[prec]["value"] / out["fp64"]["value"], 3)

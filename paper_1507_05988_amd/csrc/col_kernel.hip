@@ -101,11 +101,11 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     // reduced equations in LDS, one array per coefficient, entry (pair slot, chunk) at
     // chunk * W + slot = the thread index: the lanes of a wavefront touch consecutive 8- or
     // 16-byte words at every access (also at the +-h neighbours of the reduction), so no two
-    // lanes of a group share a bank
-    c2<R> *q_l = reinterpret_cast<c2<R> *>(smem_raw);
-    c2<R> *q_u = q_l + W * S;
-    c2<R> *q_r0 = q_u + W * S;
-    c2<R> *q_r1 = q_r0 + W * S;
+    // lanes of a group share a bank.  Two sets of the four arrays: each reduction level reads
+    // one set and writes the other, so a level needs one barrier instead of two.
+    const int ws = W * S;
+    c2<R> *set_a = reinterpret_cast<c2<R> *>(smem_raw);
+    c2<R> *set_b = set_a + 4 * ws;
     const int me = t;
 
     const int slot = it.p0 + pl;          // columns slot and nt - slot
@@ -242,17 +242,17 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
 
     // ---- one cyclic-reduction step: eliminate X_{2k-1} (the previous chunk's last equation)
     // and X_{2k+1} (this chunk's) from this chunk's first equation.  Chunk 0 has l0 = 0.
-    q_l[me] = l1;
-    q_u[me] = u1;
-    q_r0[me] = r1_1;
-    q_r1[me] = r1_2;
+    set_a[me] = l1;
+    set_a[ws + me] = u1;
+    set_a[2 * ws + me] = r1_1;
+    set_a[3 * ws + me] = r1_2;
     __syncthreads();
     c2<R> pl1 = czero<R>(), pu1 = czero<R>(), pr1 = czero<R>(), pr2 = czero<R>();
     if (k > 0) {
-        pl1 = q_l[me - W];
-        pu1 = q_u[me - W];
-        pr1 = q_r0[me - W];
-        pr2 = q_r1[me - W];
+        pl1 = set_a[me - W];
+        pu1 = set_a[ws + me - W];
+        pr1 = set_a[2 * ws + me - W];
+        pr2 = set_a[3 * ws + me - W];
     }
     c2<R> yl, yu, yr1, yr2;  // Y_{k-1}, Y_{k+1} coefficients and right-hand sides, unit diagonal
     {
@@ -265,28 +265,29 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
         yr1 = cmul<R>(cmsub<R>(cmsub<R>(r0_1, l0, pr1), u0, r1_1), idg);
         yr2 = cmul<R>(cmsub<R>(cmsub<R>(r0_2, l0, pr2), u0, r1_2), idg);
     }
-    __syncthreads();
 
-    // ---- parallel cyclic reduction on the S equations Y_k of each column pair
-    q_l[me] = yl;
-    q_u[me] = yu;
-    q_r0[me] = yr1;
-    q_r1[me] = yr2;
+    // ---- parallel cyclic reduction on the S equations Y_k of each column pair (set b holds
+    // the current level; set a was last read before the barrier below)
+    c2<R> *cur = set_b, *nxt = set_a;
+    cur[me] = yl;
+    cur[ws + me] = yu;
+    cur[2 * ws + me] = yr1;
+    cur[3 * ws + me] = yr2;
     __syncthreads();
     for (int h = 1; h < S; h <<= 1) {
         c2<R> ll = czero<R>(), lu = czero<R>(), lr1 = czero<R>(), lr2 = czero<R>();
         c2<R> hl = czero<R>(), hu = czero<R>(), hr1 = czero<R>(), hr2 = czero<R>();
         if (k - h >= 0) {
-            ll = q_l[me - h * W];
-            lu = q_u[me - h * W];
-            lr1 = q_r0[me - h * W];
-            lr2 = q_r1[me - h * W];
+            ll = cur[me - h * W];
+            lu = cur[ws + me - h * W];
+            lr1 = cur[2 * ws + me - h * W];
+            lr2 = cur[3 * ws + me - h * W];
         }
         if (k + h < S) {
-            hl = q_l[me + h * W];
-            hu = q_u[me + h * W];
-            hr1 = q_r0[me + h * W];
-            hr2 = q_r1[me + h * W];
+            hl = cur[me + h * W];
+            hu = cur[ws + me + h * W];
+            hr1 = cur[2 * ws + me + h * W];
+            hr2 = cur[3 * ws + me + h * W];
         }
         // eq_k - l_k eq_{k-h} - u_k eq_{k+h}, then renormalise (operator part shared)
         const c2<R> dg = cmsub<R>(cmsub<R>(mk<R>(R(1), R(0)), yl, lu), yu, hl);
@@ -297,19 +298,22 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
         yr2 = cmul<R>(cmsub<R>(cmsub<R>(yr2, yl, lr2), yu, hr2), idg);
         yl = mk<R>(-nl.x, -nl.y);
         yu = mk<R>(-nu.x, -nu.y);
+        // the other set was last read one level ago, before the previous barrier
+        nxt[me] = yl;
+        nxt[ws + me] = yu;
+        nxt[2 * ws + me] = yr1;
+        nxt[3 * ws + me] = yr2;
         __syncthreads();
-        q_l[me] = yl;
-        q_u[me] = yu;
-        q_r0[me] = yr1;
-        q_r1[me] = yr2;
-        __syncthreads();
+        c2<R> *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
     }
     // x_first of both columns; x_last from this chunk's last equation and the next chunk's first
     const c2<R> xf1 = yr1, xf2 = yr2;
     c2<R> nf1 = czero<R>(), nf2 = czero<R>();
     if (k + 1 < S) {
-        nf1 = q_r0[me + W];
-        nf2 = q_r1[me + W];
+        nf1 = cur[2 * ws + me + W];
+        nf2 = cur[3 * ws + me + W];
     }
     const c2<R> xl1 = cmsub<R>(cmsub<R>(r1_1, l1, xf1), u1, nf1);
     const c2<R> xl2 = cmsub<R>(cmsub<R>(r1_2, l1, xf2), u1, nf2);
@@ -352,7 +356,7 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
     const int S = (nr + L - 1) / L;
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
-    const size_t shm = 4 * sizeof(c2<R>) * (size_t)W * S;
+    const size_t shm = 8 * sizeof(c2<R>) * (size_t)W * S;
     if (a.dir == COL_RADIAL)
         hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1,
                               0, a);

@@ -642,7 +642,7 @@ def main():
     ap.add_argument("--tune-cache", default=SHIPPED_TILES,
                     help="tune cache of column tiles per nr (tuned where it lacks an entry)")
     ap.add_argument("--retune", action="store_true", help="tune every column tile anew")
-    ap.add_argument("--lanes", type=int, default=4,
+    ap.add_argument("--lanes", type=int, default=6,
                     help="concurrent instance groups of the sweep plans (fcn_options.lanes)")
     ap.add_argument("--only-headline", action="store_true",
                     help="only the headline sweep in the headline mode (for profiler runs)")

@@ -619,6 +619,14 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 #pragma unroll
                 for (int k = 0; k < E; k++) v[k] = row_lds[lpad(tr + k * T)];
             }
+        } else if constexpr (NOABS && DO_A) {
+            // Kerr phase only: the rotations leave |A| unchanged, so NL(dz_n/2) o NL(dz_{n-1}/2)
+            // is one rotation by (dz_{n-1} + dz_n)/2 times the Kerr rate of the same intensity,
+            // and the diagnostics of A^n are those of that intensity
+            c2<R> unused = czero<R>();
+            const R hab = DO_B ? R(0.5 * dz_a + 0.5 * dz_b) : ha;
+            nl_sub_step<R, T, E, NOABS, false>(v, unused, in, hab, true, DO_D, false, false, acc, tr, sh,
+                                               &a.state->unstable);
         } else {
             c2<R> unused = czero<R>();
             int32_t *unst = &a.state->unstable;

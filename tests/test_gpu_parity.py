@@ -534,6 +534,30 @@ def test_step_splitting_is_exact(precision, nr, ipk):
     assert np.array_equal(p.unpack(f1)[0].view(view), q.unpack(f2)[0].view(view))
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32_cn64", 2e-6)])
+def test_step_splitting_kerr_only_agrees_to_rounding(precision, tol):
+    """Kerr-only launches apply the two nonlinear half steps of a fused row pass as one rotation
+    (the rotations leave |A| unchanged), so step(n) then step(m) differs from step(n+m), where
+    they are two rotations, by rounding only; and the fused run matches the oracle."""
+    inst = wl.config_small(nr=64, nt=256)
+    a0 = wl.gaussian_field(inst)
+    if precision != "fp64":
+        a0 = a0.astype(np.complex64)
+    p = _plan(inst, precision)
+    f1 = p.pack(a0)
+    p.step(f1, 7)
+    q = _plan(inst, precision)
+    f2 = q.pack(a0)
+    q.step(f2, 3)
+    q.step(f2, 4)
+    p.sync()
+    q.sync()
+    x, y = p.unpack(f1)[0].astype(np.complex128), q.unpack(f2)[0].astype(np.complex128)
+    assert relmax(x, y) < tol
+    want = oracle.propagate(inst, a0.astype(np.complex128), 7)
+    assert werr(x, want) < (1e-12 if precision == "fp64" else 7e-6)
+
+
 def test_nonfinite_is_reported():
     inst = wl.config_small(nr=16, nt=64)
     plan = _plan(inst, "fp64")

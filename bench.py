@@ -630,73 +630,13 @@ def full_model_measurement(torch, args):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--headline-precision", default="fp32_cn64", choices=["fp32_cn64", "fp32"],
-                    help="mode of the headline line: fp32_cn64 (within 1e-5 of FP64 on every pulse of the "
-                         "sweep) or fp32 (faster; its largest pulse misses 1e-5)")
-    ap.add_argument("--tune-cache", default=SHIPPED_TILES,
-                    help="tune cache of column tiles per nr (tuned where it lacks an entry)")
-    ap.add_argument("--retune", action="store_true", help="tune every column tile anew")
-    ap.add_argument("--lanes", type=int, default=6,
-                    help="concurrent instance groups of the sweep plans (fcn_options.lanes)")
-    ap.add_argument("--only-headline", action="store_true",
-                    help="only the headline sweep in the headline mode (for profiler runs)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--no-full-model", action="store_true")
-    ap.add_argument("--no-parareal", action="store_true")
-    ap.add_argument("--no-net", action="store_true")
-    ap.add_argument("--no-paper-shapes", action="store_true")
-    ap.add_argument("--no-long-pulse", action="store_true")
-    ap.add_argument("--no-cartesian", action="store_true")
-    ap.add_argument("--long-pulse-checkpoints", default="100,1000,10000",
-                    help="comma-separated step counts of the long-distance pulse checkpoints")
-    ap.add_argument("--only-net", action="store_true",
-                    help="only the learned coarse network's inference and training rates (one JSON line)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 512 MiB device-to-device copy 10 times (the known-size "
-                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: this build runs the "
-              "z-step on a single MI355X (multi-GPU sharding is a design note, not implemented).",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.steps < 2:
-        print("--steps must be >= 2", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    if args.only_net:
-        print(json.dumps({"coarse_net": coarse_net_measurement(torch)}), flush=True)
-        return
-
-    if args.copy_calibration:
-        src = torch.ones(64 * 2 ** 20, dtype=torch.complex64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(10):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "reps": 10}))
-        return
-
-    insts, pts, sw = sweep_measurement(torch, args)
-    hp = args.headline_precision
-    h = sw[hp]
-    value = pts * h["steps"] / h["sec"]
-    ms_per_step = h["sec"] * 1e3 / h["steps"]
-
-    # ---- roofline of the dominant kernel: the kernel template with the longest total time per
-    # step (with several lanes a template serves several launches of a step): its average bytes
-    # per launch over its average launch duration, which is what rocprofv3's per-kernel average
-    # duration of the same run measures
-    launches = h["launches"]
+def dominant_roofline(hp, launches):
+    """Roofline of the dominant kernel: the kernel template with the longest total time per step
+    (with several lanes a template serves several launches of a step): its average bytes per
+    launch over its average launch duration.  The launch durations come from the per-launch timed
+    steps, which run the launches one after another (each kernel alone on the GPU); rocprofv3's
+    per-kernel average over a run of such steps (`--launch-timing-only`) measures the same.
+    Annotates `launches` with kernel names, bytes and GB/s."""
     by_kernel = {}
     for L in launches:
         L["kernel"] = kernel_name(hp, L)
@@ -729,6 +669,99 @@ def main():
     # before HBM, which the "valu" object beside the HBM figure shows
     roofline.update(kernel=dom_name, kernel_ms=round(avg_ms, 6), launches_per_step=dom["launches"],
                     bytes_per_launch=round(avg_bytes), kernel_ms_per_step=round(dom["ms"], 6), target_frac=0.6)
+    return roofline
+
+
+def launch_timing_only(torch, args):
+    """Only the per-launch timing of the headline plan: two timed steps to warm up, then the timed
+    steps whose launch durations the roofline uses, every dispatch eager and one after another,
+    so a rocprofv3 kernel trace of this run averages the same dispatches the events time."""
+    from paper_1507_05988_amd import fcn
+    from paper_1507_05988_amd import workloads as wl
+
+    hp = args.headline_precision
+    insts = wl.config_batch()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = fcn.Plan(insts, precision=hp, use_graph=True, stream=stream, tune_cache=args.tune_cache,
+                        lanes=args.lanes)
+        f = plan.pack([wl.gaussian_field(i, np.complex64) for i in insts])
+        plan.step_timed_launches(f, 2)
+        launches = plan.step_timed_launches(f, 20)
+        plan.sync()
+    return {"launches": launches, "roofline": dominant_roofline(hp, launches)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--headline-precision", default="fp32_cn64", choices=["fp32_cn64", "fp32"],
+                    help="mode of the headline line: fp32_cn64 (within 1e-5 of FP64 on every pulse of the "
+                         "sweep) or fp32 (faster; its largest pulse misses 1e-5)")
+    ap.add_argument("--tune-cache", default=SHIPPED_TILES,
+                    help="tune cache of column tiles per nr (tuned where it lacks an entry)")
+    ap.add_argument("--retune", action="store_true", help="tune every column tile anew")
+    ap.add_argument("--lanes", type=int, default=6,
+                    help="concurrent instance groups of the sweep plans (fcn_options.lanes)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the headline sweep in the headline mode (for profiler runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-full-model", action="store_true")
+    ap.add_argument("--no-parareal", action="store_true")
+    ap.add_argument("--no-net", action="store_true")
+    ap.add_argument("--no-paper-shapes", action="store_true")
+    ap.add_argument("--no-long-pulse", action="store_true")
+    ap.add_argument("--no-cartesian", action="store_true")
+    ap.add_argument("--long-pulse-checkpoints", default="100,1000,10000",
+                    help="comma-separated step counts of the long-distance pulse checkpoints")
+    ap.add_argument("--launch-timing-only", action="store_true",
+                    help="only the headline plan's per-launch timing and the roofline of its dominant kernel "
+                         "(the run to profile for the kernel trace that the roofline's durations match)")
+    ap.add_argument("--only-net", action="store_true",
+                    help="only the learned coarse network's inference and training rates (one JSON line)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy 10 times (the known-size "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: this build runs the "
+              "z-step on a single MI355X (multi-GPU sharding is a design note, not implemented).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 2:
+        print("--steps must be >= 2", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.only_net:
+        print(json.dumps({"coarse_net": coarse_net_measurement(torch)}), flush=True)
+        return
+    if args.launch_timing_only:
+        print(json.dumps(launch_timing_only(torch, args)), flush=True)
+        return
+
+    if args.copy_calibration:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.complex64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "reps": 10}))
+        return
+
+    insts, pts, sw = sweep_measurement(torch, args)
+    hp = args.headline_precision
+    h = sw[hp]
+    value = pts * h["steps"] / h["sec"]
+    ms_per_step = h["sec"] * 1e3 / h["steps"]
+
+    launches = h["launches"]
+    roofline = dominant_roofline(hp, launches)
 
     out = {
         "metric": METRIC,
@@ -778,21 +811,31 @@ def main():
                                             for L in r["launches"]],
                                "accuracy_vs_fp64": sweep_errors(insts, r["fields"], ref, r["diags"], dref)}
     del sw
+    def progress(what):
+        print(f"bench: {what}", file=sys.stderr, flush=True)
+
     if not args.only_headline:
+        progress("extras")
         if not args.no_full_model:
+            progress("full-model pulse")
             out["full_model_pulse"] = full_model_measurement(torch, args)
         if not args.no_paper_shapes:
+            progress("paper grids")
             out["paper_shapes"] = paper_shapes_measurement(torch, args.tune_cache)
         if not args.no_cartesian:
+            progress("Cartesian pulse")
             out["cartesian_3d"] = cartesian_measurement(torch, args.tune_cache)
         if not args.no_long_pulse:
             out["long_pulse"] = long_pulse_measurement(torch, [int(x) for x in args.long_pulse_checkpoints.split(",")])
         if not args.no_parareal:
+            progress("parareal")
             out["parareal"] = parareal_measurement(torch, "fp32_cn64")
             out["parareal_fp32_storage"] = parareal_measurement(torch, "fp32_storage")
         if not args.no_net:
+            progress("network")
             out["coarse_net"] = coarse_net_measurement(torch)
         if not args.no_cpu_baseline:
+            progress("CPU baseline")
             out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)

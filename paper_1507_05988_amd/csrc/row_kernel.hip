@@ -550,6 +550,17 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     }
     int64_t n = 0;
     if constexpr (BOOK) n = a.state->cnt_row;
+    // adaptive mode: the largest phase rate of this thread's rows (first thread of a row slot),
+    // kept while consecutive rows belong to one instance and max-reduced into the instance's
+    // slot when the instance changes and at the end (an atomic per run of rows, not per row)
+    int phi_inst = -1;
+    double phi_run = 0.0;
+    auto flush_phi = [&]() {
+        if (phi_inst < 0) return;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(phi_run);
+        atomicMax(&a.phi_slot[(n & 1) * a.batch + phi_inst], bits);
+        if (a.seed_slots) atomicMax(&a.phi_slot[((n - 1) & 1) * a.batch + phi_inst], bits);
+    };
 
     for (int grp = blockIdx.x; grp * RPW < a.nitems; grp += gridDim.x) {
     const int item_idx = grp * RPW + rw;
@@ -643,14 +654,16 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
                 rd[2] = acc.rmax;
                 rd[3] = acc.phimax;
                 if (!(acc.sum <= 1.0e300)) atomicOr(&a.state->nonfinite, 1);  // NaN or overflow
-                // the phase-rate slots feed the adaptive rule only; in the other modes the atomics
-                // (one per row, all rows of an instance on one address) would only cost time
+                // the phase-rate slots feed the adaptive rule only (all rows of an instance
+                // share one slot, so the rows' maxima are combined before the atomic)
                 if (BOOK && a.dz_mode == DZ_ADAPTIVE) {
-                    atomicMax(&a.phi_slot[(n & 1) * a.batch + it.inst],
-                              (unsigned long long)__double_as_longlong(acc.phimax));
-                    if (a.seed_slots)
-                        atomicMax(&a.phi_slot[((n - 1) & 1) * a.batch + it.inst],
-                                  (unsigned long long)__double_as_longlong(acc.phimax));
+                    if (it.inst != phi_inst) {
+                        flush_phi();
+                        phi_inst = it.inst;
+                        phi_run = acc.phimax;
+                    } else {
+                        phi_run = fmax(phi_run, acc.phimax);
+                    }
                 }
             }
         }
@@ -677,6 +690,7 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     }
     }  // rows of this workgroup
     if constexpr (BOOK) {
+        flush_phi();
         if (blockIdx.x == 0 && tid == 0) a.state->cnt_col = n;
     }
 }

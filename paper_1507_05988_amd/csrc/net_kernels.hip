@@ -179,13 +179,22 @@ __global__ void __launch_bounds__(256) conv5_mfma_kernel(const bf16_t *__restric
     const int y0 = blockIdx.y * MF_TH, x0 = blockIdx.x * MF_TW;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
-    for (int idx = tid; idx < CIN * SH * SW; idx += 256) {
-        const int c = idx / (SH * SW), rem = idx % (SH * SW);
+    // a thread stages 8 channels of one pixel: 8 coalesced 2-byte loads (lanes on consecutive
+    // pixels), one 16-byte LDS store
+    for (int idx = tid; idx < (CIN / 8) * SH * SW; idx += 256) {
+        const int g = idx / (SH * SW), rem = idx % (SH * SW);
         const int yy = rem / SW, xx = rem % SW;
         const int gy = y0 + yy, gx = x0 + xx;
-        uint16_t v = 0;
-        if (gy < Hin && gx < Win) v = in[(((size_t)b * CIN + c) * Hin + gy) * Win + gx].v;
-        s_in[(yy * SW + xx) * PIXS + c] = v;
+        const bool ok = gy < Hin && gx < Win;
+        uint32_t h[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) h[i] = ok ? in[(((size_t)b * CIN + 8 * g + i) * Hin + gy) * Win + gx].v : 0u;
+        uint4 v;
+        v.x = h[0] | (h[1] << 16);
+        v.y = h[2] | (h[3] << 16);
+        v.z = h[4] | (h[5] << 16);
+        v.w = h[6] | (h[7] << 16);
+        *reinterpret_cast<uint4 *>(&s_in[(yy * SW + xx) * PIXS + 8 * g]) = v;
     }
     __syncthreads();
 
@@ -195,24 +204,35 @@ __global__ void __launch_bounds__(256) conv5_mfma_kernel(const bf16_t *__restric
 #pragma unroll
         for (int ct = 0; ct < 4; ct++) acc[pt][ct] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
     const int n = lane & 15, kg = lane >> 4;
-    for (int t = 0; t < 25; t++) {
+    // step it = t KC + kc: tap t, input channels 32 kc .. 32 kc + 31.  The weight fragments of
+    // step it + 1 are loaded while step it's products run (they come from L2, the latency two
+    // wavefronts per SIMD would otherwise leave exposed).
+    constexpr int NIT = 25 * KC;
+    uint4 wc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++) wc[ct] = wA[ct * 64 + lane];
+    for (int it = 0; it < NIT; it++) {
+        const int t = it / KC, kc = it % KC;
         const int ky = t / 5, kx = t % 5;
+        uint4 wn[4];
+        if (it + 1 < NIT) {
 #pragma unroll
-        for (int kc = 0; kc < KC; kc++) {
-            bf16x8_t a[4];
+            for (int ct = 0; ct < 4; ct++) wn[ct] = wA[((it + 1) * 4 + ct) * 64 + lane];
+        }
+        bf16x8_t a[4];
 #pragma unroll
-            for (int ct = 0; ct < 4; ct++) {
-                const uint4 w = wA[((t * KC + kc) * 4 + ct) * 64 + lane];
-                a[ct] = __builtin_bit_cast(bf16x8_t, w);
-            }
+        for (int ct = 0; ct < 4; ct++) a[ct] = __builtin_bit_cast(bf16x8_t, wc[ct]);
 #pragma unroll
-            for (int pt = 0; pt < 4; pt++) {
-                const uint4 xv = *reinterpret_cast<const uint4 *>(
-                    &s_in[((wave + ky) * SW + 16 * pt + n + kx) * PIXS + 32 * kc + 8 * kg]);
-                const bf16x8_t bx = __builtin_bit_cast(bf16x8_t, xv);
+        for (int pt = 0; pt < 4; pt++) {
+            const uint4 xv = *reinterpret_cast<const uint4 *>(
+                &s_in[((wave + ky) * SW + 16 * pt + n + kx) * PIXS + 32 * kc + 8 * kg]);
+            const bf16x8_t bx = __builtin_bit_cast(bf16x8_t, xv);
 #pragma unroll
-                for (int ct = 0; ct < 4; ct++) acc[pt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ct], bx, acc[pt][ct], 0, 0, 0);
-            }
+            for (int ct = 0; ct < 4; ct++) acc[pt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ct], bx, acc[pt][ct], 0, 0, 0);
+        }
+        if (it + 1 < NIT) {
+#pragma unroll
+            for (int ct = 0; ct < 4; ct++) wc[ct] = wn[ct];
         }
     }
 

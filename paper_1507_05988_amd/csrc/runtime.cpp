@@ -43,12 +43,11 @@ constexpr double kPi = 3.14159265358979323846;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-#ifndef FCN_ROW_GROUPS
-#define FCN_ROW_GROUPS 1024
-#endif
-// Workgroups of a row-kernel launch at most (4 per CU of the 256; 1024 measured faster than
-// 2048, 4096 and one workgroup per row group on the batched sweep).
-constexpr int kRowGroups = FCN_ROW_GROUPS;
+// Workgroups of a row-kernel launch at most: 1024 (4 per CU of the 256), and 512 from nt = 4096,
+// where a workgroup's twiddle table (nt entries, twice with twiddle pairs) is worth staging for
+// more rows (the batched sweep's 4096-point rows: 50.8 against 54.1 us per launch; 1024 stays
+// faster for the shorter rows, and measured faster than 2048, 4096 and one workgroup per row group).
+constexpr int row_groups_for(int nt) { return nt >= 4096 ? 512 : 1024; }
 
 struct RowBucket {
     int lane;
@@ -459,9 +458,9 @@ fcn_status build_plan(fcn_plan_t p) {
                 b.scan &= ~RK_NOABS;
         }
         // the row kernel steps through row groups (blockIdx.x, + gridDim.x, ...), so a workgroup
-        // stages its twiddle table once for several rows: at most kRowGroups workgroups
+        // stages its twiddle table once for several rows: at most row_groups_for(nt) workgroups
         const int rpw = row_rows_per_group(b.nt, row_elems_for(b.nt, row_fp64_arith(p->precision)));
-        b.grid = std::min((b.nitems + rpw - 1) / rpw, kRowGroups);
+        b.grid = std::min((b.nitems + rpw - 1) / rpw, row_groups_for(b.nt));
         p->row_buckets.push_back(b);
     }
     // column work lists, one bucket per nr; tiles from the options, else the tune cache, else

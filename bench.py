@@ -168,7 +168,8 @@ def kernel_name(precision, launch):
     r = "float" if precision == "fp32" else "double"
     st = "double" if precision == "fp64" else "float"
     cart = "true" if launch["pass"] in ("col_x", "col_y") else "false"
-    return f"col_kernel<{r}, {st}, {launch['tile'][0]}, {launch['tile'][1]}, {cart}>"
+    # the step's spectrum is in pair order (last template argument)
+    return f"col_kernel<{r}, {st}, {launch['tile'][0]}, {launch['tile'][1]}, {cart}, true>"
 
 
 def sweep_run(torch, insts, precision, steps, warmup, tune_cache, lanes, graph=True):

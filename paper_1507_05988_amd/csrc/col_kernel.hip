@@ -11,12 +11,17 @@
 // c_m and f_m use (1 + 1/2m): the centred 1/r dA/dr term adds +1/(2m dr^2) to the A_{m+1}
 // coefficient (Eqs. diff2-diff3); the printed (1 - 1/2m) would cancel it.
 //
-// Layout: the spectrum is [nr][nt] with p contiguous.  Frequencies p and nt - p have the same
-// matrices (only omega_p^2 enters), so a thread solves the pair together: the elimination
-// factors, pivots and reduced-system coefficients depend on the operator only and are
-// computed once for both right-hand sides.  A workgroup takes W adjacent pair slots
+// Layout: the spectrum is [nr][nt], each row's nt values contiguous.  Frequencies p and nt - p
+// have the same matrices (only omega_p^2 enters), so a thread solves the pair together: the
+// elimination factors, pivots and reduced-system coefficients depend on the operator only and
+// are computed once for both right-hand sides.  A workgroup takes W adjacent pair slots
 // s = p0 .. p0+W-1 (columns s and nt - s; s = 0 and s = nt/2 are their own partners) and all nr
-// rows, so lanes read W consecutive complex values of a row in each of the two column groups.
+// rows.  Within a z-step the row pass leaves each row in pair order (PAIRS): entries 2s and
+// 2s + 1 hold columns s and nt - s (0 < s < nt/2), entries 0 and 1 columns 0 and nt/2.  A lane
+// then moves both columns of its pair with one load and one store per row and the W lanes of a
+// tile cover 2W contiguous values (64 bytes of FP32 spectrum at W = 4, where the natural order
+// gives two 32-byte pieces at p0 and nt - p0 - W + 1; a copy with this tile geometry runs at
+// 6.4 against 4.2 TB/s).  The stand-alone CN stage works on a natural-order spectrum.
 // The tridiagonal solve is a partitioned ("divide and conquer") elimination without
 // pivoting, so each element is read once and written once:
 //   1. thread (s, k) owns rows [kL, kL+L) of its two columns: it forms the right-hand sides
@@ -74,8 +79,16 @@ __device__ __forceinline__ c2<R> cmsub(c2<R> a, c2<R> b, c2<R> c) {
     return mk<R>(fma(-b.x, c.x, fma(b.y, c.y, a.x)), fma(-b.x, c.y, fma(-b.y, c.x, a.y)));
 }
 
-// R: arithmetic precision; ST: storage precision of the spectrum (see the row kernel).
-template <typename R, typename ST, int W, int L, bool CART>
+// The two columns of a pair slot in pair order, moved as one 16-byte (FP32) or two 16-byte
+// (FP64) accesses.
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(c2<T>)))) cpair {
+    c2<T> a, b;
+};
+
+// R: arithmetic precision; ST: storage precision of the spectrum (see the row kernel);
+// PAIRS: the spectrum is in pair order.
+template <typename R, typename ST, int W, int L, bool CART, bool PAIRS>
 __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     static_assert(L >= 4, "at least two interior rows per chunk");
     extern __shared__ unsigned char smem_raw[];
@@ -129,18 +142,34 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const R bi_ax = R(4) * s - g;      // Im b, axis row
     const double *rc = a.rowcoef + 2 * (int64_t)in.rowcoef_off;
 
-    c2<ST> *col1 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + line_off + p1;
-    c2<ST> *col2 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + line_off + p2;
+    c2<ST> *line0 = reinterpret_cast<c2<ST> *>(a.field) + in.field_off + line_off;
+    c2<ST> *col1 = line0 + p1;
+    c2<ST> *col2 = line0 + p2;
+    // pair order: the slot's pair entry (columns 0 and nt/2 share entry 0; the lone column nt/2
+    // is its second half) and the row stride in pairs (rs is even: nt is)
+    const bool second = p1 == nt / 2;
+    cpair<ST> *pcol = reinterpret_cast<cpair<ST> *>(line0) + (second ? 0 : p1);
+    const int64_t prs = rs / 2;
     const int m0 = k * L;
 
     // ---- load rows m0-1 .. m0+L (halo included) of both columns; rows outside [0, nr) read as 0
+    // (the lone columns 0 and nt/2 solve their own column twice in natural order; in pair order
+    // the second right-hand side of slot 0 is column nt/2, solved alongside and not stored)
     c2<ST> x1[L + 2], x2[L + 2];
 #pragma unroll
     for (int i = 0; i < L + 2; i++) {
         const int m = m0 - 1 + i;
         const bool in_range = live && m >= 0 && m < nr;
-        x1[i] = in_range ? col1[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
-        x2[i] = in_range ? col2[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
+        if constexpr (PAIRS) {
+            cpair<ST> v;
+            v.a = v.b = mk<ST>(ST(0), ST(0));
+            if (in_range) v = pcol[(int64_t)m * prs];
+            x1[i] = second ? v.b : v.a;
+            x2[i] = v.b;
+        } else {
+            x1[i] = in_range ? col1[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
+            x2[i] = in_range ? col2[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
+        }
     }
 
     // Row m of M_abc as (l, b, u) = (i lr, 1 + i bi, i ur) and of M_def x, computed on the fly.
@@ -336,8 +365,19 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     for (int i = 0; i < L; i++) {
         const int m = m0 + i;
         if (live && m < nr) {
-            col1[(int64_t)m * rs] = ccast<ST, R>(o1[i]);
-            if (store2) col2[(int64_t)m * rs] = ccast<ST, R>(o2[i]);
+            if constexpr (PAIRS) {
+                if (store2) {
+                    cpair<ST> v;
+                    v.a = ccast<ST, R>(o1[i]);
+                    v.b = ccast<ST, R>(o2[i]);
+                    pcol[(int64_t)m * prs] = v;
+                } else {
+                    reinterpret_cast<c2<ST> *>(pcol + (int64_t)m * prs)[second ? 1 : 0] = ccast<ST, R>(o1[i]);
+                }
+            } else {
+                col1[(int64_t)m * rs] = ccast<ST, R>(o1[i]);
+                if (store2) col2[(int64_t)m * rs] = ccast<ST, R>(o2[i]);
+            }
         }
     }
 
@@ -357,12 +397,19 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
     const int threads = W * S;
     if (threads > 512) return hipErrorInvalidValue;
     const size_t shm = 8 * sizeof(c2<R>) * (size_t)W * S;
-    if (a.dir == COL_RADIAL)
-        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1,
-                              0, a);
+    const bool cart = a.dir != COL_RADIAL;
+    if (!cart && a.pair_order)
+        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false, true>), dim3(grid), dim3(threads), (uint32_t)shm, s,
+                              e0, e1, 0, a);
+    else if (!cart)
+        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false, false>), dim3(grid), dim3(threads), (uint32_t)shm, s,
+                              e0, e1, 0, a);
+    else if (a.pair_order)
+        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, true, true>), dim3(grid), dim3(threads), (uint32_t)shm, s,
+                              e0, e1, 0, a);
     else
-        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, true>), dim3(grid), dim3(threads), (uint32_t)shm, s, e0, e1,
-                              0, a);
+        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, true, false>), dim3(grid), dim3(threads), (uint32_t)shm, s,
+                              e0, e1, 0, a);
     return hipGetLastError();
 }
 
@@ -386,6 +433,10 @@ static hipError_t launch_col_p(int w, int l, int nr, const ColArgs &a, int grid,
     if (w == 2 && l == 6) return launch_col_t<R, ST, 2, 6>(nr, a, grid, s, e0, e1);
     if (w == 4 && l == 6) return launch_col_t<R, ST, 4, 6>(nr, a, grid, s, e0, e1);
     if (w == 8 && l == 6) return launch_col_t<R, ST, 8, 6>(nr, a, grid, s, e0, e1);
+    if (w == 1 && l == 4) return launch_col_t<R, ST, 1, 4>(nr, a, grid, s, e0, e1);
+    if (w == 2 && l == 4) return launch_col_t<R, ST, 2, 4>(nr, a, grid, s, e0, e1);
+    if (w == 4 && l == 4) return launch_col_t<R, ST, 4, 4>(nr, a, grid, s, e0, e1);
+    if (w == 8 && l == 4) return launch_col_t<R, ST, 8, 4>(nr, a, grid, s, e0, e1);
     return hipErrorInvalidValue;
 }
 

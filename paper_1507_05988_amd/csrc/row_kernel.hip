@@ -517,6 +517,13 @@ struct RowCfg {
     static_assert(!PAIR || sizeof(R) == 4, "twiddle pairs are for FP32 arithmetic");
 };
 
+// Position of frequency p in a pair-order row (see RK_FFT_OUT): column s at 2s, column nt - s at
+// 2s + 1, columns 0 and nt/2 at 0 and 1.
+template <int NT>
+__device__ __forceinline__ int pair_pos(int p) {
+    return p < NT / 2 ? 2 * p : (p == NT / 2 ? 1 : 2 * (NT - p) + 1);
+}
+
 // R: arithmetic precision; ST: storage precision of the field (ST = float with R = double is
 // the FP32-storage mode: FP64 arithmetic, FP32 loads and stores).
 template <typename R, typename ST, int NT, int E, int FLAGS>
@@ -530,6 +537,10 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     __shared__ c2<R> twl[Cfg::TWN];
     __shared__ RowScratch sh;
     constexpr bool FFTS = (FLAGS & (RK_IFFT_IN | RK_FFT_OUT)) != 0;
+    // a z-step's spectrum is in pair order, the stand-alone transform stages' natural
+    constexpr bool PAIR_ORDER = (FLAGS & (RK_NL_A | RK_NL_B)) != 0;
+    constexpr bool PAIRS_IN = PAIR_ORDER && (FLAGS & RK_IFFT_IN) != 0;
+    constexpr bool PAIRS_OUT = PAIR_ORDER && (FLAGS & RK_FFT_OUT) != 0;
 
     const int tid = threadIdx.x;
     const int tr = tid % T;
@@ -587,7 +598,10 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
 
     c2<R> v[E];
 #pragma unroll
-    for (int k = 0; k < E; k++) v[k] = active ? ccast<R, ST>(g[tr + k * T]) : czero<R>();
+    for (int k = 0; k < E; k++) {
+        const int p = tr + k * T;
+        v[k] = active ? ccast<R, ST>(g[PAIRS_IN ? pair_pos<NT>(p) : p]) : czero<R>();
+    }
 
     if constexpr ((FLAGS & RK_IFFT_IN) != 0) {
         row_fft<R, NT, E, +1, Cfg::TW_LDS, Cfg::PAIR>(v, row_lds, tr, twp);
@@ -674,7 +688,10 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     if constexpr ((FLAGS & RK_STORE) != 0) {
         if (active) {
 #pragma unroll
-            for (int k = 0; k < E; k++) g[tr + k * T] = ccast<ST, R>(v[k]);
+            for (int k = 0; k < E; k++) {
+                const int p = tr + k * T;
+                g[PAIRS_OUT ? pair_pos<NT>(p) : p] = ccast<ST, R>(v[k]);
+            }
         }
     }
 

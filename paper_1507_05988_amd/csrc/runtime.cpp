@@ -237,7 +237,7 @@ void round_unit_f32(double c, double s, float out[2]) {
 
 bool col_tiles_supported(int w, int l) {
     return ((w == 1 || w == 2 || w == 4 || w == 8 || w == 16) && (l == 8 || l == 16)) || (w == 32 && l == 8) ||
-           ((w == 1 || w == 2 || w == 4 || w == 8) && l == 6);
+           ((w == 1 || w == 2 || w == 4 || w == 8) && (l == 4 || l == 6));
 }
 
 // Column tile choice: frequencies per workgroup W and rows per thread L.
@@ -625,6 +625,7 @@ hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0
         ColArgs a = col_args(p, field, b);
         a.dir = b.dir;
         a.use_stage_len = stage;
+        a.pair_order = stage ? 0 : 1;  // a z-step's spectrum is in pair order, the CN stage's natural
         a.stage_len = stage_len;
         hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, lane_stream(p, lane),
                                   lev ? lev[2 * bi] : (bi == 0 ? e0 : nullptr),
@@ -732,10 +733,14 @@ fcn_status run_sequence(fcn_plan_t p, void *field, int64_t nsteps, double *diag,
     return FCN_OK;
 }
 
+// The column pass moves a frequency pair of the pair-order spectrum with 16-byte accesses.
+bool field_aligned(const void *field) { return ((uintptr_t)field & 15) == 0; }
+
 fcn_status run_steps(fcn_plan_t p, void *field, int64_t nsteps, double *diag, int diag_every, double *dz_log,
                      int replay) {
     if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
     if (!field) return fail(p, FCN_E_ARG, "field is NULL");
+    if (!field_aligned(field)) return fail(p, FCN_E_ARG, "field is not 16-byte aligned");
     if (nsteps < 0) return fail(p, FCN_E_ARG, "nsteps < 0");
     if (replay && (!dz_log || p->opt.adaptive)) return fail(p, FCN_E_ARG, "replay needs a dz log and fixed mode");
     if (nsteps == 0 && !diag) return FCN_OK;
@@ -854,7 +859,8 @@ fcn_status fcn_plan_create(const fcn_instance *inst, int32_t batch, const fcn_op
         delete p;
         return FCN_E_ARG;
     }
-    if (p->opt.col_rows && p->opt.col_rows != 6 && p->opt.col_rows != 8 && p->opt.col_rows != 16) {
+    if (p->opt.col_rows && p->opt.col_rows != 4 && p->opt.col_rows != 6 && p->opt.col_rows != 8 &&
+        p->opt.col_rows != 16) {
         delete p;
         return FCN_E_ARG;
     }
@@ -1030,6 +1036,7 @@ fcn_status fcn_step_scratch(fcn_plan_t p, void *field_dev, int64_t nsteps, void 
     if (!p) return FCN_E_ARG;
     p->err.clear();
     if (!field_dev) return fail(p, FCN_E_ARG, "field is NULL");
+    if (!field_aligned(field_dev)) return fail(p, FCN_E_ARG, "field is not 16-byte aligned");
     if (nsteps < 0) return fail(p, FCN_E_ARG, "nsteps < 0");
     if (p->ws_bytes > FCN_SCRATCH_BYTES)
         return fail(p, FCN_E_SIZE, "plan needs %zu bytes of workspace, the static scratch holds %u", p->ws_bytes,
@@ -1075,6 +1082,7 @@ fcn_status fcn_step_timed(fcn_plan_t p, void *field_dev, int64_t nsteps, double 
     p->err.clear();
     if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
     if (!field_dev || !row_ms || !col_ms || !total_ms) return fail(p, FCN_E_ARG, "NULL argument");
+    if (!field_aligned(field_dev)) return fail(p, FCN_E_ARG, "field is not 16-byte aligned");
     if (nsteps < 2 || nsteps > 100000) return fail(p, FCN_E_ARG, "nsteps must be in [2, 100000]");
     // Steady steps s = 0 .. mid-1 each run a column pass then a fused row pass; each pass is
     // bracketed by events recorded at its kernels' own start and end.
@@ -1123,6 +1131,7 @@ fcn_status fcn_step_timed_launches(fcn_plan_t p, void *field_dev, int64_t nsteps
     p->err.clear();
     if (!p->bound) return fail(p, FCN_E_STATE, "plan is not bound to a workspace");
     if (!field_dev || !n_launches) return fail(p, FCN_E_ARG, "NULL argument");
+    if (!field_aligned(field_dev)) return fail(p, FCN_E_ARG, "field is not 16-byte aligned");
     if (nsteps < 2 || nsteps > 10000) return fail(p, FCN_E_ARG, "nsteps must be in [2, 10000]");
     const int nrow = (int)p->row_buckets.size(), ncol = (int)p->col_buckets.size(), nl = nrow + ncol;
     *n_launches = nl;

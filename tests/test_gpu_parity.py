@@ -91,7 +91,7 @@ def test_cn_stage(precision, nr):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("tiles", [(8, 8), (16, 16), (4, 16), (32, 8), (16, 8), (2, 8), (2, 16), (1, 8), (1, 16),
-                                   (8, 6), (4, 6), (2, 6), (1, 6)])
+                                   (8, 6), (4, 6), (2, 6), (1, 6), (8, 4), (4, 4), (2, 4), (1, 4)])
 def test_cn_stage_tiles(precision, tiles):
     nr, nt = 120, 128  # W * ceil(nr/L) stays within 512 threads for every tile
     if precision == "fp64" and tiles[1] == 16:

@@ -22,13 +22,17 @@ import tempfile
 import numpy as np
 
 # (W, L) pairs built into the library; FP64 arithmetic (also the column solve of fp32_cn64)
-# takes L = 8 or 6 (L = 16 needs twice the registers of the FP32 solve and spills; L = 6 keeps
-# three wavefronts per SIMD)
+# takes L = 8, 6 or 4 (L = 16 needs twice the registers of the FP32 solve and spills; L = 6 keeps
+# three wavefronts per SIMD, L = 4 four)
 CANDIDATES = {
-    "fp32": [(4, 8), (4, 16), (8, 8), (8, 16), (16, 8), (16, 16), (32, 8), (2, 16), (1, 16), (2, 8), (1, 8)],
-    "fp64": [(4, 8), (8, 8), (16, 8), (32, 8), (2, 8), (1, 8), (8, 6), (4, 6), (2, 6), (1, 6)],
-    "fp32_storage": [(4, 8), (8, 8), (16, 8), (32, 8), (2, 8), (1, 8), (8, 6), (4, 6), (2, 6), (1, 6)],
-    "fp32_cn64": [(4, 8), (8, 8), (16, 8), (32, 8), (2, 8), (1, 8), (8, 6), (4, 6), (2, 6), (1, 6)],
+    "fp32": [(4, 8), (4, 16), (8, 8), (8, 16), (16, 8), (16, 16), (32, 8), (2, 16), (1, 16), (2, 8), (1, 8),
+             (8, 4), (4, 4), (2, 4)],
+    "fp64": [(4, 8), (8, 8), (16, 8), (32, 8), (2, 8), (1, 8), (8, 6), (4, 6), (2, 6), (1, 6),
+             (8, 4), (4, 4), (2, 4), (1, 4)],
+    "fp32_storage": [(4, 8), (8, 8), (16, 8), (32, 8), (2, 8), (1, 8), (8, 6), (4, 6), (2, 6), (1, 6),
+                     (8, 4), (4, 4), (2, 4), (1, 4)],
+    "fp32_cn64": [(4, 8), (8, 8), (16, 8), (32, 8), (2, 8), (1, 8), (8, 6), (4, 6), (2, 6), (1, 6),
+                  (8, 4), (4, 4), (2, 4), (1, 4)],
 }
 MAX_THREADS = 512
 

@@ -571,6 +571,24 @@ def test_nonfinite_is_reported():
     plan.sync()  # the flag is cleared once reported
 
 
+def test_misaligned_field_is_rejected():
+    """The step entry points move frequency pairs of the spectrum with 16-byte accesses and
+    reject a field pointer that is not 16-byte aligned (here 8 bytes into an allocation)."""
+    import ctypes
+    import torch
+
+    inst = wl.config_small(nr=16, nt=64)
+    plan = _plan(inst, "fp32")
+    f = plan.pack(wl.gaussian_field(inst, np.complex64))
+    buf = torch.zeros(f.numel() + 1, dtype=f.dtype, device=f.device)
+    ptr = ctypes.c_void_p(buf.data_ptr() + 8)
+    for call in (lambda: plan.lib.fcn_step(plan._h, ptr, 1),
+                 lambda: plan.lib.fcn_propagate(plan._h, ptr, 1, None, 0, None, 0)):
+        assert call() == fcn.FCN_E_ARG
+    plan.step(f, 1)  # the aligned field still steps
+    plan.sync()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_cn64"])
 def test_density_instability_is_reported(precision):
     """A 30 fs spike above the RK4 density step's stability limit (1.99e18 W/m^2 on the

@@ -56,16 +56,19 @@ namespace fcn {
 // 1 / z for the pivots of the elimination.  They depend on the operator only, never on the
 // field, and |z|^2 stays of order one (the matrix has Hermitian part I after the diagonal
 // similarity above), so the hardware reciprocal refined by Newton-Raphson steps
-// r <- r + r (1 - d r) replaces the IEEE division sequence: two steps from the
-// reciprocal's estimate reach the FP64 rounding level, one step the FP32 level.
-template <typename R>
+// r <- r + r (1 - d r) replaces the IEEE division sequence: each step squares the relative
+// error of the estimate (at most 2^-24.4 for the FP64 one, measured on 4M values over 40
+// binades), so two steps reach the FP64 rounding level and one step 2^-48.7, far below the
+// rounding of an FP32 spectrum (FP64_FULL = false: FP64 arithmetic on FP32 storage); one step
+// from the FP32 estimate reaches the FP32 level.
+template <typename R, bool FP64_FULL = true>
 __device__ __forceinline__ c2<R> pivot_rcp(c2<R> z) {
     const R d = z.x * z.x + z.y * z.y;
     R r;
     if constexpr (sizeof(R) == 8) {
         r = __builtin_amdgcn_rcp(d);
         r = fma(r, fma(-d, r, 1.0), r);
-        r = fma(r, fma(-d, r, 1.0), r);
+        if constexpr (FP64_FULL) r = fma(r, fma(-d, r, 1.0), r);
     } else {
         r = __builtin_amdgcn_rcpf(d);
         r = fmaf(r, fmaf(-d, r, 1.0f), r);
@@ -92,6 +95,7 @@ template <typename R, typename ST, int W, int L, bool CART, bool PAIRS>
 __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     static_assert(L >= 4, "at least two interior rows per chunk");
     extern __shared__ unsigned char smem_raw[];
+    constexpr bool FULL = sizeof(ST) == sizeof(R);  // pivots to the arithmetic's full precision
 
     // Workgroups are dispatched round-robin over the 8 XCDs (b -> XCD b mod 8).  Give each
     // XCD a contiguous range of column tiles so tiles sharing 128-byte lines (W*sizeof < 128)
@@ -152,23 +156,22 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     const int64_t prs = rs / 2;
     const int m0 = k * L;
 
-    // ---- load rows m0-1 .. m0+L (halo included) of both columns; rows outside [0, nr) read as 0
-    // (the lone columns 0 and nt/2 solve their own column twice in natural order; in pair order
-    // the second right-hand side of slot 0 is column nt/2, solved alongside and not stored)
+    // ---- load rows m0-1 .. m0+L (halo included) of both columns (the lone columns 0 and nt/2
+    // solve their own column twice in natural order; in pair order the second right-hand side
+    // of slot 0 is column nt/2, solved alongside and not stored).  A row outside [0, nr) is read
+    // from the nearest row inside: such a value only ever meets an exact zero coefficient (the
+    // axis row's lower neighbour, the identity rows from nr - 1 on), so any finite value serves.
     c2<ST> x1[L + 2], x2[L + 2];
 #pragma unroll
     for (int i = 0; i < L + 2; i++) {
-        const int m = m0 - 1 + i;
-        const bool in_range = live && m >= 0 && m < nr;
+        const int m = min(max(m0 - 1 + i, 0), nr - 1);
         if constexpr (PAIRS) {
-            cpair<ST> v;
-            v.a = v.b = mk<ST>(ST(0), ST(0));
-            if (in_range) v = pcol[(int64_t)m * prs];
+            const cpair<ST> v = pcol[(int64_t)m * prs];
             x1[i] = second ? v.b : v.a;
             x2[i] = v.b;
         } else {
-            x1[i] = in_range ? col1[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
-            x2[i] = in_range ? col2[(int64_t)m * rs] : mk<ST>(ST(0), ST(0));
+            x1[i] = col1[(int64_t)m * rs];
+            x2[i] = col2[(int64_t)m * rs];
         }
     }
 
@@ -217,7 +220,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     {
         R lr, bi, ur;
         row_coef(1, lr, bi, ur);
-        c2<R> ip = pivot_rcp<R>(mk<R>(R(1), bi));
+        c2<R> ip = pivot_rcp<R, FULL>(mk<R>(R(1), bi));
         mu[1] = cmul_i<R>(ip, ur);
         sp[1] = cmul_i<R>(ip, lr);
         rp1[1] = cmul<R>(rhs_of(x1, 1, lr, bi, ur), ip);
@@ -227,7 +230,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
             row_coef(i, lr, bi, ur);
             // pivot b_i - l_i mu_{i-1}
             const c2<R> lmu = cmul_i<R>(mu[i - 1], lr);
-            ip = pivot_rcp<R>(mk<R>(R(1) - lmu.x, bi - lmu.y));
+            ip = pivot_rcp<R, FULL>(mk<R>(R(1) - lmu.x, bi - lmu.y));
             mu[i] = cmul_i<R>(ip, ur);
             sp[i] = cmul<R>(cmul_i<R>(sp[i - 1], -lr), ip);
             rp1[i] = cmul<R>(csub<R>(rhs_of(x1, i, lr, bi, ur), cmul_i<R>(rp1[i - 1], lr)), ip);
@@ -255,14 +258,14 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     c2<R> l0, u0, r0_1, r0_2, l1, u1, r1_1, r1_2;
     {
         const c2<R> uA = cmul_i<R>(A, ur0);
-        const c2<R> idg = pivot_rcp<R>(mk<R>(R(1) - uA.x, bi0 - uA.y));
+        const c2<R> idg = pivot_rcp<R, FULL>(mk<R>(R(1) - uA.x, bi0 - uA.y));
         l0 = cmul_i<R>(idg, lr0);
         u0 = cmul<R>(cmul_i<R>(C, -ur0), idg);
         r0_1 = cmul<R>(csub<R>(rhs0_1, cmul_i<R>(D1, ur0)), idg);
         r0_2 = cmul<R>(csub<R>(rhs0_2, cmul_i<R>(D2, ur0)), idg);
 
         const c2<R> lC = cmul_i<R>(Cl, lrL);
-        const c2<R> idg1 = pivot_rcp<R>(mk<R>(R(1) - lC.x, biL - lC.y));
+        const c2<R> idg1 = pivot_rcp<R, FULL>(mk<R>(R(1) - lC.x, biL - lC.y));
         l1 = cmul<R>(cmul_i<R>(Al, -lrL), idg1);
         u1 = cmul_i<R>(idg1, urL);
         r1_1 = cmul<R>(csub<R>(rhsL_1, cmul_i<R>(Dl1, lrL)), idg1);
@@ -270,23 +273,24 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     }
 
     // ---- one cyclic-reduction step: eliminate X_{2k-1} (the previous chunk's last equation)
-    // and X_{2k+1} (this chunk's) from this chunk's first equation.  Chunk 0 has l0 = 0.
+    // and X_{2k+1} (this chunk's) from this chunk's first equation.  Chunk 0 has l0 = 0
+    // exactly (the axis or wall row has no lower coupling), so it reads its own entry in place
+    // of a missing neighbour: 0 times a finite value.  The reduction below does the same at both
+    // ends: an equation whose neighbour at distance h is outside [0, S) has an exactly zero
+    // coupling to it (true for h = 1, the first chunk's l0 and the last chunk's u1 being 0, and
+    // kept by every level, whose new couplings are products with the old ones).
     set_a[me] = l1;
     set_a[ws + me] = u1;
     set_a[2 * ws + me] = r1_1;
     set_a[3 * ws + me] = r1_2;
     __syncthreads();
-    c2<R> pl1 = czero<R>(), pu1 = czero<R>(), pr1 = czero<R>(), pr2 = czero<R>();
-    if (k > 0) {
-        pl1 = set_a[me - W];
-        pu1 = set_a[ws + me - W];
-        pr1 = set_a[2 * ws + me - W];
-        pr2 = set_a[3 * ws + me - W];
-    }
+    const int prev = k > 0 ? me - W : me;
+    const c2<R> pl1 = set_a[prev], pu1 = set_a[ws + prev];
+    const c2<R> pr1 = set_a[2 * ws + prev], pr2 = set_a[3 * ws + prev];
     c2<R> yl, yu, yr1, yr2;  // Y_{k-1}, Y_{k+1} coefficients and right-hand sides, unit diagonal
     {
         const c2<R> dg = cmsub<R>(cmsub<R>(mk<R>(R(1), R(0)), l0, pu1), u0, l1);
-        const c2<R> idg = pivot_rcp<R>(dg);
+        const c2<R> idg = pivot_rcp<R, FULL>(dg);
         const c2<R> nl = cmul<R>(cmul<R>(l0, pl1), idg);
         const c2<R> nu = cmul<R>(cmul<R>(u0, u1), idg);
         yl = mk<R>(-nl.x, -nl.y);
@@ -304,23 +308,13 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     cur[3 * ws + me] = yr2;
     __syncthreads();
     for (int h = 1; h < S; h <<= 1) {
-        c2<R> ll = czero<R>(), lu = czero<R>(), lr1 = czero<R>(), lr2 = czero<R>();
-        c2<R> hl = czero<R>(), hu = czero<R>(), hr1 = czero<R>(), hr2 = czero<R>();
-        if (k - h >= 0) {
-            ll = cur[me - h * W];
-            lu = cur[ws + me - h * W];
-            lr1 = cur[2 * ws + me - h * W];
-            lr2 = cur[3 * ws + me - h * W];
-        }
-        if (k + h < S) {
-            hl = cur[me + h * W];
-            hu = cur[ws + me + h * W];
-            hr1 = cur[2 * ws + me + h * W];
-            hr2 = cur[3 * ws + me + h * W];
-        }
+        const int lo = k - h >= 0 ? me - h * W : me;
+        const int hi = k + h < S ? me + h * W : me;
+        const c2<R> ll = cur[lo], lu = cur[ws + lo], lr1 = cur[2 * ws + lo], lr2 = cur[3 * ws + lo];
+        const c2<R> hl = cur[hi], hu = cur[ws + hi], hr1 = cur[2 * ws + hi], hr2 = cur[3 * ws + hi];
         // eq_k - l_k eq_{k-h} - u_k eq_{k+h}, then renormalise (operator part shared)
         const c2<R> dg = cmsub<R>(cmsub<R>(mk<R>(R(1), R(0)), yl, lu), yu, hl);
-        const c2<R> idg = pivot_rcp<R>(dg);
+        const c2<R> idg = pivot_rcp<R, FULL>(dg);
         const c2<R> nl = cmul<R>(cmul<R>(yl, ll), idg);
         const c2<R> nu = cmul<R>(cmul<R>(yu, hu), idg);
         yr1 = cmul<R>(cmsub<R>(cmsub<R>(yr1, yl, lr1), yu, hr1), idg);
@@ -339,11 +333,8 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     }
     // x_first of both columns; x_last from this chunk's last equation and the next chunk's first
     const c2<R> xf1 = yr1, xf2 = yr2;
-    c2<R> nf1 = czero<R>(), nf2 = czero<R>();
-    if (k + 1 < S) {
-        nf1 = cur[2 * ws + me + W];
-        nf2 = cur[3 * ws + me + W];
-    }
+    const int next = k + 1 < S ? me + W : me;  // the last chunk has u1 = 0
+    const c2<R> nf1 = cur[2 * ws + next], nf2 = cur[3 * ws + next];
     const c2<R> xl1 = cmsub<R>(cmsub<R>(r1_1, l1, xf1), u1, nf1);
     const c2<R> xl2 = cmsub<R>(cmsub<R>(r1_2, l1, xf2), u1, nf2);
 

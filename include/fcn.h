@@ -191,9 +191,9 @@ fcn_status fcn_plan_bind(fcn_plan_t plan, void *workspace_dev, size_t workspace_
  * inverse FFT (Eq. antifourier); the nonlinear half step integrates the electron density along t by
  * RK4 (Eq. ionization) from rho = 0 at t_min and multiplies by exp(dz/2 N) (Eqs. Anhalf,
  * Anhalf1, nonlinearpart).  nsteps >= 0.  field_dev must be 16-byte aligned (the column solve
- * moves a frequency pair p, nt - p as one access: inside a step each row's spectrum is held
- * with the two columns of a pair adjacent; before and after the call the field is in natural
- * time order).  Errors: FCN_E_STATE before bind; FCN_E_ARG for a NULL or misaligned field.
+ * moves a frequency pair p, nt - p as one access: inside a step each row's FP32 spectrum is
+ * held with the two columns of a pair adjacent; before and after the call the field is in
+ * natural time order).  Errors: FCN_E_STATE before bind; FCN_E_ARG for a NULL or misaligned field.
  * fcn_propagate, fcn_step_timed, fcn_step_timed_launches and fcn_step_scratch take the same
  * field. */
 fcn_status fcn_step(fcn_plan_t plan, void *field_dev, int64_t nsteps);

@@ -16,12 +16,13 @@
 // elimination factors, pivots and reduced-system coefficients depend on the operator only and
 // are computed once for both right-hand sides.  A workgroup takes W adjacent pair slots
 // s = p0 .. p0+W-1 (columns s and nt - s; s = 0 and s = nt/2 are their own partners) and all nr
-// rows.  Within a z-step the row pass leaves each row in pair order (PAIRS): entries 2s and
+// rows.  Within a z-step the row pass leaves each FP32 row in pair order (PAIRS): entries 2s and
 // 2s + 1 hold columns s and nt - s (0 < s < nt/2), entries 0 and 1 columns 0 and nt/2.  A lane
 // then moves both columns of its pair with one load and one store per row and the W lanes of a
 // tile cover 2W contiguous values (64 bytes of FP32 spectrum at W = 4, where the natural order
 // gives two 32-byte pieces at p0 and nt - p0 - W + 1; a copy with this tile geometry runs at
-// 6.4 against 4.2 TB/s).  The stand-alone CN stage works on a natural-order spectrum.
+// 6.4 against 4.2 TB/s).  An FP64 spectrum (16-byte values: the natural order already gives
+// 64-byte pieces) and the stand-alone CN stage stay in natural order.
 // The tridiagonal solve is a partitioned ("divide and conquer") elimination without
 // pivoting, so each element is read once and written once:
 //   1. thread (s, k) owns rows [kL, kL+L) of its two columns: it forms the right-hand sides
@@ -82,8 +83,7 @@ __device__ __forceinline__ c2<R> cmsub(c2<R> a, c2<R> b, c2<R> c) {
     return mk<R>(fma(-b.x, c.x, fma(b.y, c.y, a.x)), fma(-b.x, c.y, fma(-b.y, c.x, a.y)));
 }
 
-// The two columns of a pair slot in pair order, moved as one 16-byte (FP32) or two 16-byte
-// (FP64) accesses.
+// The two columns of a pair slot in pair order, moved as one 16-byte access.
 template <typename T>
 struct __attribute__((aligned(2 * sizeof(c2<T>)))) cpair {
     c2<T> a, b;
@@ -389,14 +389,21 @@ static hipError_t launch_col_t(int nr, const ColArgs &a, int grid, hipStream_t s
     if (threads > 512) return hipErrorInvalidValue;
     const size_t shm = 8 * sizeof(c2<R>) * (size_t)W * S;
     const bool cart = a.dir != COL_RADIAL;
-    if (!cart && a.pair_order)
-        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false, true>), dim3(grid), dim3(threads), (uint32_t)shm, s,
-                              e0, e1, 0, a);
-    else if (!cart)
+    if constexpr (sizeof(ST) == 4) {  // pair order is an FP32 spectrum's only
+        if (a.pair_order) {
+            if (!cart)
+                hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false, true>), dim3(grid), dim3(threads),
+                                      (uint32_t)shm, s, e0, e1, 0, a);
+            else
+                hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, true, true>), dim3(grid), dim3(threads),
+                                      (uint32_t)shm, s, e0, e1, 0, a);
+            return hipGetLastError();
+        }
+    } else {
+        if (a.pair_order) return hipErrorInvalidValue;
+    }
+    if (!cart)
         hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, false, false>), dim3(grid), dim3(threads), (uint32_t)shm, s,
-                              e0, e1, 0, a);
-    else if (a.pair_order)
-        hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, true, true>), dim3(grid), dim3(threads), (uint32_t)shm, s,
                               e0, e1, 0, a);
     else
         hipExtLaunchKernelGGL((col_kernel<R, ST, W, L, true, false>), dim3(grid), dim3(threads), (uint32_t)shm, s,

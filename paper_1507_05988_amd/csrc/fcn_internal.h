@@ -90,11 +90,12 @@ enum : int {
     RK_DIAG = 4,        // diagnostics of the state after RK_NL_A (A^n)
     RK_NL_B = 8,        // nonlinear half step with dz_n
     RK_FFT_OUT = 16,    // forward FFT, write the spectrum.  With RK_NL_A or RK_NL_B (a z-step's
-                        // launches) the spectrum read by RK_IFFT_IN and written by RK_FFT_OUT is
-                        // in pair order: entry 2s holds column s and entry 2s + 1 column nt - s
-                        // (0 < s < nt/2), entries 0 and 1 columns 0 and nt/2 (the column pass
-                        // then moves a frequency pair with one access); the stand-alone
-                        // transform stages use natural order
+                        // launches) an FP32 spectrum read by RK_IFFT_IN and written by RK_FFT_OUT
+                        // is in pair order: entry 2s holds column s and entry 2s + 1 column
+                        // nt - s (0 < s < nt/2), entries 0 and 1 columns 0 and nt/2 (the column
+                        // pass then moves a frequency pair with one 16-byte access); an FP64
+                        // spectrum (16-byte values, already 64 contiguous bytes per 4-column
+                        // run) and the stand-alone transform stages use natural order
     RK_STORE = 32,      // write the row back (time domain unless RK_FFT_OUT)
     RK_STAGE_LEN = 64,  // stage test: NL_B uses the explicit length argument as its exponent
     RK_SCAN = 128,      // some instance of the launch has a density term: contiguous-chunk
@@ -143,7 +144,7 @@ struct ColArgs {
     DevState *state;
     int32_t use_stage_len;
     int32_t dir;              // COL_RADIAL, COL_X or COL_Y (the launch's systems)
-    int32_t pair_order;       // 1: the spectrum is in pair order (within a z-step; see RK_FFT_OUT)
+    int32_t pair_order;       // 1: the spectrum is in pair order (FP32, within a z-step; see RK_FFT_OUT)
     int32_t pad;
     double stage_len;
 };

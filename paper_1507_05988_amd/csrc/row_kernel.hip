@@ -537,8 +537,9 @@ __global__ void __launch_bounds__(row_threads(NT, E)) row_kernel(RowArgs a) {
     __shared__ c2<R> twl[Cfg::TWN];
     __shared__ RowScratch sh;
     constexpr bool FFTS = (FLAGS & (RK_IFFT_IN | RK_FFT_OUT)) != 0;
-    // a z-step's spectrum is in pair order, the stand-alone transform stages' natural
-    constexpr bool PAIR_ORDER = (FLAGS & (RK_NL_A | RK_NL_B)) != 0;
+    // a z-step's FP32 spectrum is in pair order; an FP64 one, and the stand-alone transform
+    // stages', in natural order
+    constexpr bool PAIR_ORDER = (FLAGS & (RK_NL_A | RK_NL_B)) != 0 && sizeof(ST) == 4;
     constexpr bool PAIRS_IN = PAIR_ORDER && (FLAGS & RK_IFFT_IN) != 0;
     constexpr bool PAIRS_OUT = PAIR_ORDER && (FLAGS & RK_FFT_OUT) != 0;
 

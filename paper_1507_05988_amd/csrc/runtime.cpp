@@ -625,7 +625,8 @@ hipError_t col_pass(fcn_plan_t p, void *field, int stage, double stage_len = 0.0
         ColArgs a = col_args(p, field, b);
         a.dir = b.dir;
         a.use_stage_len = stage;
-        a.pair_order = stage ? 0 : 1;  // a z-step's spectrum is in pair order, the CN stage's natural
+        // a z-step's FP32 spectrum is in pair order; an FP64 one and the CN stage's natural
+        a.pair_order = stage == 0 && p->precision != FCN_FP64 ? 1 : 0;
         a.stage_len = stage_len;
         hipError_t e = launch_col(p->precision, b.w, b.l, b.nr, a, b.nitems, lane_stream(p, lane),
                                   lev ? lev[2 * bi] : (bi == 0 ? e0 : nullptr),

@@ -108,6 +108,23 @@ def test_full_model_run(precision, tol):
     assert e < tol and el < ELEMENTWISE * tol
 
 
+@pytest.mark.parametrize("precision", ["fp32_cn64", "fp32"])
+@pytest.mark.parametrize("tiles", [(1, 4), (2, 6), (4, 8), (8, 4), (16, 8), (32, 8)])
+def test_pair_order_steps_tiles(precision, tiles):
+    """Two full-model steps of a 21 x 13 x 64 beam through the pair-order spectrum (the x and
+    y solves move columns s and nt - s with one access; columns 0 and nt/2 in the first and last
+    tile of every line) with every kind of column tile, against the oracle from the same FP32
+    input: 2e-6 in the field norm (two steps of the FP32 per-step bound)."""
+    say(f"cartesian pair order steps {precision} tiles {tiles}")
+    inst = _inst(nx=21, ny=13, nt=64)
+    a0 = cart.propagate(inst, wl.cartesian_field(inst), 2).astype(np.complex64)  # structure in x, y, t
+    got = _run(inst, precision, 2, a0, col_tile=tiles[0], col_rows=tiles[1]).astype(np.complex128)
+    want = cart.propagate(inst, a0.astype(np.complex128), 2)
+    e = l2err(got, want)
+    say(f"  field {e:.3e}")
+    assert e < 2e-6
+
+
 def test_full_model_run_plain_fp32_reported_not_at_target():
     inst = _inst(nx=63, ny=47, nt=128)
     a0 = wl.cartesian_field(inst).astype(np.complex64)
